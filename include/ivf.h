@@ -1,0 +1,226 @@
+/*
+ * ivf.h - C ABI of the MI355X (gfx950) inverted-file spherical k-means library.
+ *
+ * The method is the inverted-file Lloyd iteration of Aoyama, Saito and Ikeda,
+ * "Inverted-File k-Means Clustering: Performance Analysis" (Algorithm 3):
+ *   assignment: every L2-normalised sparse object x_i is scored against all k
+ *     sparse unit-norm means by walking the term-major inverted file of the
+ *     means (term t -> ascending list of (cluster j, mean value m_jt)),
+ *     rho_j += x_it * m_jt; the object joins the argmax cluster (rho_max starts
+ *     at 0, strict ">", ascending j: the lowest j wins exact ties; an object
+ *     sharing no term with any mean keeps its previous cluster);
+ *   update: every mean is the member sum divided by |C_j| and then by its
+ *     2-norm; the inverted file is rebuilt from the new means with every list
+ *     in ascending cluster order.
+ * The problem statement (object set, k, initial state, iterations) follows the
+ * paper's Section "Lloyd-Type k-Means Clustering Algorithm".
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked "device" are HIP device pointers; all work is enqueued
+ *    on ivf_options.stream.  Entry points that fill an ivf_stats synchronise
+ *    that stream before returning.
+ *  - Ownership: the caller owns every buffer it passes.  The object set given
+ *    to ivf_build is BORROWED: it must stay alive and unchanged until
+ *    ivf_destroy.  The handle owns the means, the inverted file and scratch.
+ *  - Ids are 0-based; an assignment of -1 means "unassigned" (the object has
+ *    not yet shared a term with any mean).
+ *  - Errors: every call returns an ivf_status; nothing throws across the ABI.
+ *    Argument checks happen before any launch; ivf_last_error(h) gives text.
+ *  - Concurrency: one handle must not be used from two host threads at once.
+ */
+#ifndef IVF_H
+#define IVF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ivf_handle ivf_handle;
+
+typedef enum {
+    IVF_OK = 0,
+    IVF_ERR_ARG = -1,        /* bad sizes, null pointers, k out of [1, n] */
+    IVF_ERR_UNSORTED = -2,   /* term ids not strictly ascending in a row, or out of [0, d) */
+    IVF_ERR_NONFINITE = -3,  /* NaN or infinite value */
+    IVF_ERR_NEGATIVE = -4,   /* a value <= 0 (stored nonzeros must be positive) */
+    IVF_ERR_CAPACITY = -5,   /* sizes beyond the library's limits (nnz >= 2^31, ...) */
+    IVF_ERR_OOM = -6,        /* device allocation failed */
+    IVF_ERR_HIP = -7,        /* a HIP runtime call failed (text in ivf_last_error) */
+    IVF_ERR_STATE = -8       /* call order: e.g. ivf_assign before any means exist */
+} ivf_status;
+
+/* Precision of the mean values stored in the inverted file used by the
+ * assignment walk.  Scores are always accumulated in FP32; objects whose
+ * top-1/top-2 margin is inside the stated error bound are re-scored in FP64. */
+typedef enum { IVF_VAL_F32 = 0, IVF_VAL_BF16 = 1, IVF_VAL_F16 = 2 } ivf_valtype;
+
+/* Object set, CSR (the paper's sparse expression of Fig. "fig:str"(a)).
+ * indptr[n+1] (int64, indptr[0] == 0, non-decreasing, indptr[n] == nnz),
+ * indices[nnz] (int32, strictly ascending within a row, in [0, d)),
+ * values[nnz] (float32, finite, > 0).  All device pointers. */
+typedef struct {
+    int64_t n;
+    int64_t d;
+    int64_t nnz;
+    const int64_t* indptr;
+    const int32_t* indices;
+    const float* values;
+} ivf_csr;
+
+/* k means, mean-major CSR in FP64: row j lists (term, value) of mean j with
+ * strictly ascending terms.  All device pointers.  For ivf_get_means the
+ * caller allocates indptr[k+1], indices[nnz], values[nnz]. */
+typedef struct {
+    int32_t k;
+    int64_t d;
+    int64_t nnz;
+    int64_t* indptr;
+    int32_t* indices;
+    double* values;
+} ivf_means;
+
+typedef struct {
+    int32_t valtype;        /* ivf_valtype of the inverted-file values */
+    int32_t certify;        /* 1: certify every argmax, re-score uncertified objects in
+                               FP64 (assignments equal the FP64 reference); 0: take the
+                               FP32 argmax as is (for timing studies only) */
+    int32_t cluster_range;  /* clusters per LDS score tile; 0: planner's choice */
+    int32_t waves_per_wg;   /* waves (each owning one tile) per workgroup; 0: planner */
+    int32_t objects_per_item; /* objects per work-queue item; 0: planner */
+    int32_t force_rescore;  /* test hook: 1 = treat every object as uncertified */
+    void* stream;           /* hipStream_t; NULL = the null stream */
+} ivf_options;
+
+/* Fills *o with the defaults (F32, certify on, planner's choices, null stream). */
+void ivf_default_options(ivf_options* o);
+
+typedef struct {
+    /* assignment step */
+    double objective;        /* sum_i rho_{i,a_i}: certified objects contribute their
+                                FP32 score, re-scored ones their FP64 score */
+    double objective_bound;  /* relative error bound of `objective` w.r.t. the FP64
+                                objective (largest per-object bound used) */
+    int64_t changed;         /* objects whose cluster changed */
+    int64_t certified;       /* objects whose FP32 argmax was certified by the bound */
+    int64_t rescored;        /* objects re-scored in FP64 */
+    int64_t zero_overlap;    /* objects sharing no term with any mean */
+    int64_t mult_adds;       /* M = sum_i sum_h (nc)_{t(i,h)} (the paper's Eq. ivf_mult) */
+    double max_rel_err;      /* max |rho~ - rho64| / rho64 over re-scored objects' winners */
+    float assign_ms;         /* device time of the assignment step */
+    /* update step */
+    double objective_exact;  /* sum_j mu_j(old) . s_j(new member sum), FP64: the same J
+                                as `objective` computed from the update's exact sums */
+    int64_t empty_clusters;  /* clusters without members (their means are kept) */
+    int64_t nnz_means;       /* sum_j (ntm)_j after the call */
+    int64_t inexact_terms;   /* terms whose fixed-point member sums were rounded */
+    float update_ms;         /* device time of the update step */
+} ivf_stats;
+
+/*
+ * ivf_build: validate the object set, derive its term-major view and plan the
+ * launch shapes.  No means exist yet: call ivf_set_means or ivf_init_seeds.
+ *   X     object set (device pointers, borrowed, see ivf_csr)
+ *   k     number of clusters, 1 <= k <= n, k < 2^24
+ *   opts  NULL for defaults
+ *   out   receives the handle (NULL on failure)
+ * Errors: IVF_ERR_ARG, IVF_ERR_UNSORTED, IVF_ERR_NONFINITE, IVF_ERR_NEGATIVE,
+ * IVF_ERR_CAPACITY, IVF_ERR_OOM, IVF_ERR_HIP.  Synchronises the stream.
+ */
+ivf_status ivf_build(const ivf_csr* X, int32_t k, const ivf_options* opts, ivf_handle** out);
+
+/*
+ * ivf_set_means: replace the means with caller-given FP64 means (mean-major,
+ * device pointers; copied) and rebuild the inverted file (Alg. 3's M-breve).
+ * M->k must equal the handle's k and M->d its d.  Rows must hold strictly
+ * ascending terms in [0, d) and finite values.  Synchronises the stream.
+ */
+ivf_status ivf_set_means(ivf_handle* h, const ivf_means* M);
+
+/*
+ * ivf_init_seeds: initial state from k seed objects: mean j is object
+ * seeds[j] (device int32 [k], each in [0, n)) renormalised in FP64, i.e. the
+ * update step applied to the partition {seeds[j]} -> j.  Synchronises.
+ */
+ivf_status ivf_init_seeds(ivf_handle* h, const int32_t* seeds);
+
+/*
+ * ivf_assign: one assignment step (Alg. 3, assignment part) under the current
+ * means.  assign (device int32 [n]) holds the previous assignment on entry
+ * (-1 = unassigned) and the new one on return.  stats may be NULL (then the
+ * call does not synchronise); when given, its assignment fields are filled.
+ */
+ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats);
+
+/*
+ * ivf_update: one update step (Alg. 3, update part) from the assignment
+ * (device int32 [n], -1 entries ignored): exact member sums, FP64 norms and
+ * renormalisation, clusters without members keep their mean, then the
+ * inverted-file rebuild.  stats may be NULL; the update fields are filled when
+ * given.  Synchronises the stream (the new means' size sets later launches).
+ */
+ivf_status ivf_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats);
+
+/*
+ * ivf_iterate: `iters` Lloyd iterations (assignment then update).  assign as
+ * in ivf_assign.  per_iter (host, [iters]) may be NULL.
+ */
+ivf_status ivf_iterate(ivf_handle* h, int32_t iters, int32_t* assign, ivf_stats* per_iter);
+
+/*
+ * ivf_get_means: two-call copy of the current means.  With out->indptr NULL
+ * only out->k, out->d and out->nnz are filled; otherwise the caller's device
+ * buffers (indptr[k+1], indices[nnz], values[nnz], nnz from the first call)
+ * receive the mean-major FP64 means.  Synchronises.
+ */
+ivf_status ivf_get_means(ivf_handle* h, ivf_means* out);
+
+/*
+ * ivf_get_scores: per-object results of the last ivf_assign (device outputs,
+ * any may be NULL): best[n] FP32 top-1 score of the tile walk, second[n] FP32
+ * best score of any other cluster, rho[n] the score used for the objective
+ * (FP64; the FP64 re-score where one was made), flags[n] (bit 0: certified,
+ * bit 1: re-scored in FP64, bit 2: no shared term).  Synchronises.
+ */
+ivf_status ivf_get_scores(ivf_handle* h, float* best, float* second, double* rho,
+                          uint8_t* flags);
+
+/*
+ * ivf_get_plan: the launch plan chosen by ivf_build: plan[0] clusters per
+ * range (k_r), plan[1] number of ranges, plan[2] waves per workgroup,
+ * plan[3] objects per work item, plan[4] FP64 re-score range size,
+ * plan[5] FP64 re-score ranges, plan[6] LDS bytes per workgroup.
+ */
+ivf_status ivf_get_plan(const ivf_handle* h, int32_t plan[7]);
+
+/*
+ * ivf_plan_shape: the planner alone (host only, no GPU needed): for k
+ * clusters and the given options, fills plan[7] as ivf_get_plan would.
+ * Returns IVF_ERR_ARG for k < 1 or requests beyond the LDS budget.
+ */
+ivf_status ivf_plan_shape(int32_t k, const ivf_options* opts, int32_t plan[7]);
+
+/*
+ * ivf_cert_bound: the certification constants for an object of `nt`
+ * nonzeros and the given value type (host only): c[0] relative bound of an
+ * FP32 tile score against the exact score, c[1] absolute term, c[2] relative
+ * bound of the FP64 reference's own rounding.  The test certifying cluster a
+ * over every other cluster b is
+ *   (s_a - c[1]) (1 - c[2]) / (1 + c[0])  >  (s_b + c[1]) (1 + c[2]) / (1 - c[0]).
+ */
+ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]);
+
+/* Frees the handle and everything it owns (NULL is a no-op). */
+void ivf_destroy(ivf_handle* h);
+
+/* Text of the last error on h (or of the last ivf_build failure if h is NULL). */
+const char* ivf_last_error(const ivf_handle* h);
+
+/* Static name of a status code. */
+const char* ivf_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IVF_H */

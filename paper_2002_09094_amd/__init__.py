@@ -1,0 +1,180 @@
+"""Inverted-file spherical k-means on MI355X (gfx950).
+
+The product is the C-ABI library ``libivf.so`` (include/ivf.h) built from the
+HIP sources in ``csrc/``.  This package is its thin Python binding: PyTorch
+supplies device memory and streams; every step of the Lloyd iteration runs in
+the library's kernels.  There is no CPU fallback: without the built library or
+a GPU, the calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import IVF_VAL_BF16, IVF_VAL_F16, IVF_VAL_F32, IvfError, check
+
+
+def library():
+    """Load libivf.so (ImportError if it has not been built)."""
+    return _lib.get()
+
+VALTYPES = {"f32": IVF_VAL_F32, "bf16": IVF_VAL_BF16, "f16": IVF_VAL_F16}
+
+__all__ = ["IVFKMeans", "IvfError", "VALTYPES", "plan_shape", "cert_bound"]
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need_cuda(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous %s tensor" % (name, dtype))
+    return t
+
+
+def _options(valtype="f32", certify=True, cluster_range=0, waves_per_wg=0, objects_per_item=0,
+             force_rescore=False, stream=None):
+    o = _lib.ivf_options()
+    _lib.get().ivf_default_options(ctypes.byref(o))
+    o.valtype = VALTYPES[valtype] if isinstance(valtype, str) else int(valtype)
+    o.certify = 1 if certify else 0
+    o.cluster_range = int(cluster_range)
+    o.waves_per_wg = int(waves_per_wg)
+    o.objects_per_item = int(objects_per_item)
+    o.force_rescore = 1 if force_rescore else 0
+    o.stream = ctypes.c_void_p(stream) if stream else None
+    return o
+
+
+def plan_shape(k, **opts):
+    """Launch plan the library would pick for k clusters (host only)."""
+    o = _options(**opts)
+    plan = (ctypes.c_int32 * 7)()
+    check(_lib.get().ivf_plan_shape(int(k), ctypes.byref(o), plan))
+    keys = ("k_r", "ranges", "waves", "chunk", "k_r64", "ranges64", "lds_bytes")
+    return dict(zip(keys, list(plan)))
+
+
+def cert_bound(valtype, nt):
+    """(c, a, g64) certification constants for an object of nt nonzeros."""
+    c = (ctypes.c_double * 3)()
+    vt = VALTYPES[valtype] if isinstance(valtype, str) else int(valtype)
+    check(_lib.get().ivf_cert_bound(vt, int(nt), c))
+    return tuple(c)
+
+
+class IVFKMeans:
+    """One clustering instance on the current HIP device.
+
+    indptr (int64 [n+1]), indices (int32 [nnz]), values (float32 [nnz]) are CUDA
+    tensors holding the object set in CSR form; they are borrowed and must
+    outlive the instance.
+    """
+
+    def __init__(self, indptr, indices, values, d, k, *, valtype="f32", certify=True,
+                 cluster_range=0, waves_per_wg=0, objects_per_item=0, force_rescore=False,
+                 stream=None):
+        import torch
+        _need_cuda(indptr, torch.int64, "indptr")
+        _need_cuda(indices, torch.int32, "indices")
+        _need_cuda(values, torch.float32, "values")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._keep = (indptr, indices, values)
+        self.n = indptr.numel() - 1
+        self.d = int(d)
+        self.k = int(k)
+        self.nnz = indices.numel()
+        x = _lib.ivf_csr(self.n, self.d, self.nnz, _ptr(indptr), _ptr(indices), _ptr(values))
+        o = _options(valtype, certify, cluster_range, waves_per_wg, objects_per_item,
+                     force_rescore, stream)
+        h = ctypes.c_void_p()
+        check(_lib.get().ivf_build(ctypes.byref(x), self.k, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+
+    # -- state -------------------------------------------------------------
+    def set_means(self, indptr, indices, values):
+        import torch
+        _need_cuda(indptr, torch.int64, "indptr")
+        _need_cuda(indices, torch.int32, "indices")
+        _need_cuda(values, torch.float64, "values")
+        m = _lib.ivf_means(self.k, self.d, indices.numel(), _ptr(indptr), _ptr(indices),
+                           _ptr(values))
+        check(_lib.get().ivf_set_means(self._h, ctypes.byref(m)), self._h)
+
+    def init_seeds(self, seeds):
+        import torch
+        _need_cuda(seeds, torch.int32, "seeds")
+        if seeds.numel() != self.k:
+            raise ValueError("need k seeds")
+        check(_lib.get().ivf_init_seeds(self._h, _ptr(seeds)), self._h)
+
+    def get_means(self):
+        import torch
+        m = _lib.ivf_means()
+        check(_lib.get().ivf_get_means(self._h, ctypes.byref(m)), self._h)
+        nnz = m.nnz
+        dev = self._keep[0].device
+        ptr = torch.empty(self.k + 1, dtype=torch.int64, device=dev)
+        idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device=dev)
+        m2 = _lib.ivf_means(self.k, self.d, nnz, _ptr(ptr), _ptr(idx), _ptr(val))
+        check(_lib.get().ivf_get_means(self._h, ctypes.byref(m2)), self._h)
+        return ptr, idx[:nnz], val[:nnz]
+
+    def get_scores(self):
+        import torch
+        dev = self._keep[0].device
+        best = torch.empty(self.n, dtype=torch.float32, device=dev)
+        second = torch.empty(self.n, dtype=torch.float32, device=dev)
+        rho = torch.empty(self.n, dtype=torch.float64, device=dev)
+        flags = torch.empty(self.n, dtype=torch.uint8, device=dev)
+        check(_lib.get().ivf_get_scores(self._h, _ptr(best), _ptr(second), _ptr(rho),
+                                      _ptr(flags)), self._h)
+        return best, second, rho, flags
+
+    @property
+    def plan(self):
+        plan = (ctypes.c_int32 * 7)()
+        check(_lib.get().ivf_get_plan(self._h, plan), self._h)
+        keys = ("k_r", "ranges", "waves", "chunk", "k_r64", "ranges64", "lds_bytes")
+        return dict(zip(keys, list(plan)))
+
+    # -- steps -------------------------------------------------------------
+    def assign(self, assign, stats=True):
+        import torch
+        _need_cuda(assign, torch.int32, "assign")
+        st = _lib.ivf_stats() if stats else None
+        check(_lib.get().ivf_assign(self._h, _ptr(assign), ctypes.byref(st) if stats else None),
+              self._h)
+        return st.to_dict() if stats else None
+
+    def update(self, assign, stats=True):
+        import torch
+        _need_cuda(assign, torch.int32, "assign")
+        st = _lib.ivf_stats() if stats else None
+        check(_lib.get().ivf_update(self._h, _ptr(assign), ctypes.byref(st) if stats else None),
+              self._h)
+        return st.to_dict() if stats else None
+
+    def iterate(self, iters, assign, stats=True):
+        import torch
+        _need_cuda(assign, torch.int32, "assign")
+        arr = (_lib.ivf_stats * max(int(iters), 1))() if stats else None
+        check(_lib.get().ivf_iterate(self._h, int(iters), _ptr(assign), arr), self._h)
+        return [arr[i].to_dict() for i in range(int(iters))] if stats else None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.get().ivf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

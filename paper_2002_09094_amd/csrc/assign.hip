@@ -1,0 +1,423 @@
+// Assignment step of inverted-file spherical k-means (Algorithm 3, assignment
+// part) for gfx950.
+//
+//   k_walk     For each (cluster range, object): stream the object's CSR
+//              nonzeros, gather the range's slice of each term's posting list
+//              and scatter-accumulate x_t * m_jt into a per-wave FP32 LDS score
+//              tile (one wave owns one tile, so every slot is accumulated in
+//              ascending term order); a fused wave-wide pass then extracts the
+//              range's top-1 (lowest id on equal scores) and top-2 and clears
+//              the tile for the next object.
+//   k_merge    Per object: merge the ranges' records, certify the FP32 argmax
+//              with the rounding-error bound, else queue the object for FP64.
+//   k_rescore  Per queued object: recompute every score in FP64 exactly as the
+//              FP64 reference does (ascending terms, ascending clusters within
+//              a term, a separate multiply and add) and apply the argmax rule.
+//   k_objective / k_sum_final  deterministic FP64 objective and change count.
+#include "ivf_internal.h"
+#include "kernels.h"
+
+namespace ivf {
+namespace {
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ inline int32_t rl32(int32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ inline int64_t rl64(int64_t x, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(x >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline float rlf(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+__device__ inline void lds_add(float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline float widen16(uint32_t bits16, int vt) {
+    if (vt == IVF_VAL_BF16) return __uint_as_float(bits16 << 16);
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)bits16);
+}
+
+// One term's posting slice [qb, qe) scattered into the tile (F32 entries).
+__device__ inline void walk_f32(const uint2* __restrict__ P, int64_t qb, int64_t qe, float v,
+                                float* tile, int32_t base, int lane) {
+    for (int64_t q0 = qb; q0 < qe; q0 += 4 * kWave) {
+        const int64_t q = q0 + lane;
+        const bool b0 = q < qe, b1 = q + kWave < qe, b2 = q + 2 * kWave < qe,
+                   b3 = q + 3 * kWave < qe;
+        uint2 e0 = make_uint2(0, 0), e1 = e0, e2 = e0, e3 = e0;
+        if (b0) e0 = P[q];
+        if (b1) e1 = P[q + kWave];
+        if (b2) e2 = P[q + 2 * kWave];
+        if (b3) e3 = P[q + 3 * kWave];
+        if (b0) lds_add(tile + ((int32_t)e0.x - base), v * __uint_as_float(e0.y));
+        if (b1) lds_add(tile + ((int32_t)e1.x - base), v * __uint_as_float(e1.y));
+        if (b2) lds_add(tile + ((int32_t)e2.x - base), v * __uint_as_float(e2.y));
+        if (b3) lds_add(tile + ((int32_t)e3.x - base), v * __uint_as_float(e3.y));
+    }
+}
+
+// 16-bit values: entry = local cluster id (low 16 bits) | value bits (high 16).
+template <int VT>
+__device__ inline void walk_h16(const uint32_t* __restrict__ P, int64_t qb, int64_t qe, float v,
+                                float* tile, int lane) {
+    for (int64_t q0 = qb; q0 < qe; q0 += 4 * kWave) {
+        const int64_t q = q0 + lane;
+        const bool b0 = q < qe, b1 = q + kWave < qe, b2 = q + 2 * kWave < qe,
+                   b3 = q + 3 * kWave < qe;
+        uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
+        if (b0) e0 = P[q];
+        if (b1) e1 = P[q + kWave];
+        if (b2) e2 = P[q + 2 * kWave];
+        if (b3) e3 = P[q + 3 * kWave];
+        if (b0) lds_add(tile + (e0 & 0xffffu), v * widen16(e0 >> 16, VT));
+        if (b1) lds_add(tile + (e1 & 0xffffu), v * widen16(e1 >> 16, VT));
+        if (b2) lds_add(tile + (e2 & 0xffffu), v * widen16(e2 >> 16, VT));
+        if (b3) lds_add(tile + (e3 & 0xffffu), v * widen16(e3 >> 16, VT));
+    }
+}
+
+// Wave-wide merge of (best, id, second): larger best wins, lower id on equal
+// best; second collects the largest score of every other cluster.
+__device__ inline void top2_combine(float& b, int32_t& id, float& s, float ob, int32_t oid,
+                                    float os) {
+    const bool take = ob > b || (ob == b && oid >= 0 && (id < 0 || oid < id));
+    if (take) {
+        s = fmaxf(os, b);
+        b = ob;
+        id = oid;
+    } else {
+        s = fmaxf(s, ob);
+    }
+}
+
+template <int VT>
+__global__ __launch_bounds__(kWave * kMaxWaves) void k_walk(WalkArgs a) {
+    extern __shared__ float4 lds4[];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int lane = lane_id();
+    // wave index made provably uniform, so every loop below has uniform bounds
+    // and cross-lane reads always see all 64 lanes active
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    float* tile = lds + (int64_t)wv * a.tile_stride;
+    for (int s = lane * 4; s < a.tile_stride; s += 4 * kWave)
+        *reinterpret_cast<float4*>(tile + s) = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t total = a.items_per_range * a.R;
+    unsigned long long m_acc = 0;
+    // items in ascending order, round robin over the waves: all waves sweep
+    // the ranges in the same order, so a range's posting slices stay hot
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves) {
+        const int r = (int)(w / a.items_per_range);
+        const int64_t c = w - (int64_t)r * a.items_per_range;
+        const int32_t base = r * a.k_r;
+        const int32_t kr = min(a.k_r, a.k - base);
+        const int64_t i0 = c * a.chunk;
+        const int64_t i1 = min(a.n, i0 + a.chunk);
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
+            int32_t m = 0;
+            for (int64_t h0 = hb; h0 < he; h0 += kWave) {
+                const int cnt = (int)min((int64_t)kWave, he - h0);
+                float v = 0.f;
+                int64_t pb = 0, pe = 0;
+                if (lane < cnt) {
+                    const int32_t t = a.x_idx[h0 + lane];
+                    v = a.x_val[h0 + lane];
+                    const int64_t* sp = a.sub_ptr + (int64_t)t * (a.R + 1) + r;
+                    pb = sp[0];
+                    pe = sp[1];
+                }
+                for (int hh = 0; hh < cnt; ++hh) {
+                    const int64_t qb = rl64(pb, hh), qe = rl64(pe, hh);
+                    const float vv = rlf(v, hh);
+                    m += (int32_t)(qe - qb);
+                    if (VT == IVF_VAL_F32)
+                        walk_f32(reinterpret_cast<const uint2*>(a.post), qb, qe, vv, tile, base,
+                                 lane);
+                    else
+                        walk_h16<VT>(reinterpret_cast<const uint32_t*>(a.post), qb, qe, vv, tile,
+                                     lane);
+                }
+            }
+            // fused top-2 over the tile, clearing it for the next object
+            float b = 0.f, s2 = 0.f;
+            int32_t id = -1;
+            for (int s0 = lane * 4; s0 < kr; s0 += 4 * kWave) {
+                const float4 q = *reinterpret_cast<const float4*>(tile + s0);
+                *reinterpret_cast<float4*>(tile + s0) = make_float4(0.f, 0.f, 0.f, 0.f);
+                const float x[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (x[u] > b) {
+                        s2 = fmaxf(s2, b);
+                        b = x[u];
+                        id = s0 + u;
+                    } else {
+                        s2 = fmaxf(s2, x[u]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = kWave / 2; o >= 1; o >>= 1) {
+                const float ob = __shfl_xor(b, o, kWave);
+                const int32_t oid = __shfl_xor(id, o, kWave);
+                const float os = __shfl_xor(s2, o, kWave);
+                top2_combine(b, id, s2, ob, oid, os);
+            }
+            // every lane holds the same record: identical stores, no divergence
+            RangeRec rec;
+            rec.best = b;
+            rec.id = id >= 0 ? base + id : -1;
+            rec.second = s2;
+            rec.m = m;
+            a.rec[i * a.R + r] = rec;
+            m_acc += (unsigned long long)m;
+        }
+    }
+    atomicAdd(&a.cnt->mult, lane == 0 ? m_acc : 0ull);
+}
+
+__global__ void k_merge(MergeArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    float b = 0.f, s2 = 0.f;
+    int32_t id = -1;
+    int64_t m = 0;
+    for (int r = 0; r < a.R; ++r) {
+        const RangeRec rec = a.rec[i * a.R + r];
+        m += rec.m;
+        // ranges arrive in ascending cluster order: an equal best keeps the earlier
+        if (rec.best > b) {
+            s2 = fmaxf(fmaxf(s2, b), rec.second);
+            b = rec.best;
+            id = rec.id;
+        } else {
+            s2 = fmaxf(s2, rec.best);
+        }
+    }
+    const int32_t prev = a.prev[i];
+    a.best[i] = b;
+    a.best_id[i] = id;
+    a.second[i] = s2;
+    uint8_t flag;
+    if (m == 0) {                      // no term shared with any mean
+        a.assign[i] = prev;
+        a.rho[i] = 0.0;
+        flag = 4;
+        atomicAdd(&a.cnt->zero_overlap, 1ull);
+    } else {
+        double c, ab, g;
+        cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], &c, &ab, &g);
+        const bool ok = !a.force_rescore && b > 0.f &&
+                        cert_lb((double)b, c, ab, g) > cert_ub((double)s2, c, ab, g);
+        if (ok || !a.certify) {
+            a.assign[i] = id >= 0 ? id : prev;
+            a.rho[i] = (double)b;
+            flag = ok ? 1 : 0;
+            if (ok) atomicAdd(&a.cnt->certified, 1ull);
+            const double rel = c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0);
+            atomicMax(&a.cnt->max_bound_bits, (unsigned long long)__double_as_longlong(rel));
+        } else {
+            const unsigned long long slot = atomicAdd(&a.cnt->n_rescore, 1ull);
+            a.rescore_list[slot] = (int32_t)i;
+            flag = 2;
+        }
+    }
+    a.flags[i] = flag;
+}
+
+// One wave per queued object; an FP64 score tile of k_r64 clusters in LDS.
+__global__ __launch_bounds__(kWave) void k_rescore(RescoreArgs a) {
+    extern __shared__ double t64[];
+    const int lane = lane_id();
+    const int64_t nq = (int64_t)a.cnt->n_rescore;
+    for (int64_t w = blockIdx.x; w < nq; w += gridDim.x) {
+        const int64_t i = a.rescore_list[w];
+        const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
+        const int32_t prev = a.prev[i];
+        double best = 0.0;
+        int32_t bj = prev;
+        double rho_fp32_winner = -1.0;
+        const int32_t fp32_winner = a.best_id[i];
+        for (int r = 0; r < a.R64; ++r) {
+            const int32_t base = r * a.k_r64;
+            const int32_t kr = min(a.k_r64, a.k - base);
+            for (int s = lane; s < kr; s += kWave) t64[s] = 0.0;
+            for (int64_t h0 = hb; h0 < he; h0 += kWave) {
+                const int cnt = (int)min((int64_t)kWave, he - h0);
+                double v = 0.0;
+                int64_t lo = 0, hi = 0;
+                if (lane < cnt) {
+                    const int32_t t = a.x_idx[h0 + lane];
+                    v = (double)a.x_val[h0 + lane];
+                    const int64_t pb = a.ivf_ptr[t], pe = a.ivf_ptr[t + 1];
+                    // first entry with cluster >= base, then first >= base + kr
+                    int64_t l = pb, u = pe;
+                    while (l < u) {
+                        const int64_t mid = (l + u) >> 1;
+                        if (a.cid[mid] < base) l = mid + 1; else u = mid;
+                    }
+                    lo = l;
+                    u = pe;
+                    while (l < u) {
+                        const int64_t mid = (l + u) >> 1;
+                        if (a.cid[mid] < base + kr) l = mid + 1; else u = mid;
+                    }
+                    hi = l;
+                }
+                for (int hh = 0; hh < cnt; ++hh) {
+                    const int64_t qb = rl64(lo, hh), qe = rl64(hi, hh);
+                    const double vv = __longlong_as_double(rl64(__double_as_longlong(v), hh));
+                    for (int64_t q = qb + lane; q < qe; q += kWave) {
+                        const int32_t j = a.cid[q] - base;
+                        const double p = vv * a.val64[q];
+                        t64[j] = t64[j] + p;
+                    }
+                }
+            }
+            // argmax of the range: larger value, lowest cluster on equal values
+            double rb = 0.0;
+            int32_t rj = -1;
+            for (int s = lane; s < kr; s += kWave) {
+                const double x = t64[s];
+                if (x > rb) { rb = x; rj = s; }
+                if (base + s == fp32_winner) rho_fp32_winner = x;
+            }
+#pragma unroll
+            for (int o = kWave / 2; o >= 1; o >>= 1) {
+                const double ob = __shfl_xor(rb, o, kWave);
+                const int32_t oj = __shfl_xor(rj, o, kWave);
+                if (ob > rb || (ob == rb && oj >= 0 && (rj < 0 || oj < rj))) { rb = ob; rj = oj; }
+                const double ow = __shfl_xor(rho_fp32_winner, o, kWave);
+                rho_fp32_winner = fmax(rho_fp32_winner, ow);
+            }
+            // ranges in ascending order with a strict test: earlier ranges keep ties
+            if (rb > best) {
+                best = rb;
+                bj = base + rj;
+            }
+        }
+        // best, bj and rho_fp32_winner are wave-uniform: identical stores from
+        // every lane, and an idempotent max
+        a.assign[i] = best > 0.0 ? bj : prev;
+        a.rho[i] = best;
+        if (rho_fp32_winner > 0.0) {
+            const double e = fabs((double)a.best[i] - rho_fp32_winner) / rho_fp32_winner;
+            atomicMax(&a.cnt->max_err_bits, (unsigned long long)__double_as_longlong(e));
+        }
+    }
+}
+
+// Deterministic FP64 sum of rho over fixed chunks + change count.
+__global__ __launch_bounds__(256) void k_objective(const double* __restrict__ rho,
+                                                   const int32_t* __restrict__ assign,
+                                                   const int32_t* __restrict__ prev, int64_t n,
+                                                   int64_t per_block, double* __restrict__ part,
+                                                   Counters* cnt) {
+    __shared__ double sh[256];
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const int64_t b1 = min(n, b0 + per_block);
+    double acc = 0.0;
+    unsigned long long ch = 0;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
+        acc += rho[i];
+        ch += (assign[i] != prev[i]);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+    if (ch) atomicAdd(&cnt->changed, ch);
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ part, int64_t m,
+                                                   double* __restrict__ out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += 256) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_clear_counters(Counters* c) {
+    unsigned long long* p = reinterpret_cast<unsigned long long*>(c);
+    const int n = (int)(sizeof(Counters) / sizeof(unsigned long long));
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+}  // namespace
+
+hipError_t launch_clear_counters(Counters* c, hipStream_t s) {
+    k_clear_counters<<<1, 64, 0, s>>>(c);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes, int grid,
+                       hipStream_t s) {
+    const dim3 blk(kWave * waves);
+    if (valtype == IVF_VAL_F32)
+        k_walk<IVF_VAL_F32><<<grid, blk, lds_bytes, s>>>(a);
+    else if (valtype == IVF_VAL_BF16)
+        k_walk<IVF_VAL_BF16><<<grid, blk, lds_bytes, s>>>(a);
+    else
+        k_walk<IVF_VAL_F16><<<grid, blk, lds_bytes, s>>>(a);
+    return hipGetLastError();
+}
+
+const void* walk_kernel_ptr(int valtype) {
+    if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32>);
+    if (valtype == IVF_VAL_BF16) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_BF16>);
+    return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F16>);
+}
+
+hipError_t walk_set_lds_limit(int lds_bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_walk<IVF_VAL_BF16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_walk<IVF_VAL_F16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 8 * 8192);
+}
+
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
+    const int64_t blocks = (a.n + 255) / 256;
+    if (blocks > 0) k_merge<<<(unsigned)blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescore(const RescoreArgs& a, int grid, hipStream_t s) {
+    k_rescore<<<grid, kWave, (size_t)a.k_r64 * 8, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_objective(const double* rho, const int32_t* assign, const int32_t* prev,
+                            int64_t n, double* part, int nblocks, double* out, Counters* cnt,
+                            hipStream_t s) {
+    if (n <= 0) {
+        k_sum_final<<<1, 256, 0, s>>>(part, 0, out);
+        return hipGetLastError();
+    }
+    const int64_t per = (n + nblocks - 1) / nblocks;
+    k_objective<<<nblocks, 256, 0, s>>>(rho, assign, prev, n, per, part, cnt);
+    k_sum_final<<<1, 256, 0, s>>>(part, nblocks, out);
+    return hipGetLastError();
+}
+
+}  // namespace ivf

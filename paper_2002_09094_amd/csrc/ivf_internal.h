@@ -1,0 +1,110 @@
+// Internal declarations of the gfx950 IVF spherical k-means library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ivf.h"
+
+namespace ivf {
+
+constexpr int kWave = 64;
+constexpr int kLdsBytes = 160 * 1024;      // LDS per CU (and per workgroup) on gfx950
+constexpr int kMaxWaves = 16;
+
+// Launch plan of the assignment walk (see plan.cpp).
+struct Plan {
+    int32_t k = 0;
+    int32_t k_r = 0;          // clusters per FP32 score tile (one range)
+    int32_t R = 0;            // number of cluster ranges
+    int32_t waves = 0;        // waves per workgroup, each owning one tile
+    int32_t chunk = 0;        // objects per work-queue item
+    int32_t tile_stride = 0;  // floats per tile (k_r rounded up to 256)
+    int32_t k_r64 = 0;        // clusters per FP64 re-score tile
+    int32_t R64 = 0;
+    int32_t lds_bytes = 0;    // per workgroup of the walk
+};
+
+// Per (object, range) result of the walk.
+struct RangeRec {
+    float best;      // largest tile score in the range (0 if none)
+    int32_t id;      // its cluster id (global), -1 if best == 0
+    float second;    // largest score of any other cluster of the range
+    int32_t m;       // posting entries walked for this object in this range
+};
+
+// Device-side counters, cleared by a kernel before each step.
+struct Counters {
+    unsigned long long work;        // walk work queue
+    unsigned long long work64;      // re-score work queue
+    unsigned long long n_rescore;   // flagged objects
+    unsigned long long mult;        // posting entries walked
+    unsigned long long certified;
+    unsigned long long zero_overlap;
+    unsigned long long changed;
+    unsigned long long empty;
+    unsigned long long max_err_bits;   // max relative error (double bits, >= 0)
+    unsigned long long max_bound_bits; // max objective bound (double bits, >= 0)
+    unsigned long long error_flags;    // validation
+    unsigned long long pad[5];
+};
+
+// Error flags raised by the validation kernels.
+enum : unsigned {
+    kBadPtr = 1u,
+    kBadIndex = 2u,
+    kBadOrder = 4u,
+    kNonFinite = 8u,
+    kNonPositive = 16u,
+};
+
+// Certification constants: see ivf_cert_bound in ivf.h.
+__host__ __device__ inline void cert_consts(int valtype, int64_t nt, double* c, double* a,
+                                            double* g64) {
+    const double u32 = 0x1p-24, u64 = 0x1p-53;
+    double us;
+    if (valtype == IVF_VAL_F32) us = u32;
+    else if (valtype == IVF_VAL_BF16) us = 0x1p-8 + u32 + 0x1p-32;   // FP64 -> FP32 -> BF16
+    else us = 0x1p-11 + u32 + 0x1p-35;                               // FP64 -> FP32 -> FP16
+    const double n = (double)(nt > 0 ? nt : 1);
+    const double g32 = n * u32 / (1.0 - n * u32);
+    double cc = (1.0 + us) * (1.0 + g32) - 1.0;
+    *c = cc * 1.01 + 1e-15;
+    // FP16 subnormal / flushed mean values: |m~ - m| <= 2^-25 absolutely; the
+    // object's values are <= 1, so the score moves by at most nt * 2^-25.
+    *a = (valtype == IVF_VAL_F16) ? n * 0x1p-25 * (1.0 + g32) * 1.01 : 0.0;
+    *g64 = (n * u64 / (1.0 - n * u64)) * 1.01 + 1e-17;
+}
+
+__host__ __device__ inline double cert_lb(double s, double c, double a, double g) {
+    return (s - a) * (1.0 - g) / (1.0 + c);
+}
+__host__ __device__ inline double cert_ub(double s, double c, double a, double g) {
+    return (s + a) * (1.0 + g) / (1.0 - c);
+}
+
+// ----------------------------------------------------------------- primitives
+// Exclusive scan of n values (uint32 or int64) in place or out of place.
+// tmp must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp,
+                              hipStream_t s);
+hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp,
+                              hipStream_t s);
+
+// Stable LSD radix sort of (key, value) uint32 pairs on bits [0, bits).
+// Buffers: keys/vals are in-out (result lands back in keys/vals);
+// keys_alt/vals_alt are scratch of n entries; tmp holds radix_tmp_bytes(n).
+// If vals_in_first != nullptr, the first pass reads values from it instead
+// of vals (saves a copy of an immutable payload).
+size_t radix_tmp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                            uint32_t* vals_alt, int64_t n, int bits, void* tmp, hipStream_t s,
+                            const uint32_t* vals_in_first = nullptr);
+
+// Plan of the walk for k clusters.
+ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err);
+
+}  // namespace ivf

@@ -1,0 +1,168 @@
+// Argument blocks and launch wrappers of the device kernels.
+#pragma once
+
+#include "ivf_internal.h"
+
+namespace ivf {
+
+struct WalkArgs {
+    const int64_t* x_ptr;
+    const int32_t* x_idx;
+    const float* x_val;
+    int64_t n;
+    const int64_t* sub_ptr;   // [d * (R + 1)]: per term, first entry of every range
+    const void* post;         // uint2 {cluster, f32} or uint32 {local cluster | 16-bit value}
+    int32_t k, k_r, R, chunk, tile_stride;
+    int64_t items_per_range;  // ceil(n / chunk)
+    Counters* cnt;
+    RangeRec* rec;            // [n * R]
+};
+
+struct MergeArgs {
+    const int64_t* x_ptr;
+    int64_t n;
+    int32_t R;
+    int32_t valtype, certify, force_rescore;
+    const RangeRec* rec;
+    const int32_t* prev;
+    int32_t* assign;
+    double* rho;
+    float* best;
+    int32_t* best_id;
+    float* second;
+    uint8_t* flags;
+    int32_t* rescore_list;
+    Counters* cnt;
+};
+
+struct RescoreArgs {
+    const int64_t* x_ptr;
+    const int32_t* x_idx;
+    const float* x_val;
+    const int64_t* ivf_ptr;   // [d + 1]
+    const int32_t* cid;       // [nnzM] cluster of every inverted-file entry
+    const double* val64;      // [nnzM] FP64 mean value of every entry
+    int32_t k, k_r64, R64;
+    const int32_t* rescore_list;
+    const int32_t* prev;
+    int32_t* assign;
+    double* rho;
+    const float* best;
+    const int32_t* best_id;
+    Counters* cnt;
+};
+
+hipError_t launch_clear_counters(Counters* c, hipStream_t s);
+hipError_t walk_set_lds_limit(int lds_bytes);
+const void* walk_kernel_ptr(int valtype);
+hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes, int grid,
+                       hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_rescore(const RescoreArgs& a, int grid, hipStream_t s);
+hipError_t launch_objective(const double* rho, const int32_t* assign, const int32_t* prev,
+                            int64_t n, double* part, int nblocks, double* out, Counters* cnt,
+                            hipStream_t s);
+
+// ----------------------------------------------------------------- update side
+struct ObjectView {
+    const int64_t* x_ptr;
+    const int32_t* x_idx;
+    const float* x_val;
+    int64_t n, d, nnz;
+};
+
+// Validation of the object set: raises bits of Counters::error_flags.
+hipError_t launch_validate_objects(const ObjectView& x, Counters* cnt, hipStream_t s);
+// Validation of caller-given mean-major means.
+hipError_t launch_validate_means(const int64_t* ptr, const int32_t* idx, const double* val,
+                                 int32_t k, int64_t d, int64_t nnz, Counters* cnt,
+                                 hipStream_t s);
+// rowid[e] = object of entry e.
+hipError_t launch_row_ids(const int64_t* ptr, int64_t n, int32_t* rowid, hipStream_t s);
+hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s);
+hipError_t launch_copy_keys(const int32_t* in, uint32_t* out, int64_t n, hipStream_t s);
+// After sorting (term, position): term-major view of the objects.
+hipError_t launch_build_xt(const uint32_t* sorted_terms, const uint32_t* sorted_pos,
+                           const int32_t* rowid, const float* x_val, int64_t nnz,
+                           int32_t* xt_obj, int32_t* xt_term, float* xt_val, hipStream_t s);
+// Per-term fixed-point scale: every member sum of term t is exact in units of
+// 2^shift[t] unless the term's values span too wide a range (then rounded).
+hipError_t launch_term_shift(const int32_t* x_idx, const float* x_val, int64_t nnz, int64_t d,
+                             int32_t* emin, int32_t* emax, int32_t* count, int16_t* shift,
+                             Counters* cnt, hipStream_t s);
+
+struct UpdateArgs {
+    int64_t n, d, nnz;
+    int32_t k;
+    const int32_t* assign;
+    const int32_t* xt_obj;
+    const int32_t* xt_term;
+    const float* xt_val;
+    const int16_t* shift;
+    // sort buffers (nnz)
+    uint32_t* keys;
+    uint32_t* vals;
+    uint32_t* keys_alt;
+    uint32_t* vals_alt;
+    const uint32_t* iota;
+    // segments (nnz capacity)
+    uint32_t* flag;
+    uint32_t* segpos;
+    unsigned long long* seg_acc;
+    int32_t* seg_j;
+    int32_t* seg_t;
+    // clusters
+    int64_t* size;      // [k]
+    int64_t* cstart;    // [k + 1]
+    double* nrm;        // [k]
+    double* objpart;    // [k]
+    int64_t* newcnt;    // [k]
+    int64_t* scal;      // device scalars: [0] valid entries, [1] segments
+    // old means (mean-major) and new means
+    const int64_t* old_ptr;
+    const int32_t* old_idx;
+    const double* old_val;
+    int64_t* new_ptr;
+    int32_t* new_idx;
+    double* new_val;
+    int32_t* new_row;
+    Counters* cnt;
+    void* tmp;
+};
+
+// Update, first half: group entries by cluster, exact per-(cluster, term)
+// sums, sizes, norms, exact objective, new row counts and row pointers.
+hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s);
+// Update, second half: write the new mean-major means (after capacity check).
+hipError_t launch_update_fill(UpdateArgs& a, hipStream_t s);
+hipError_t launch_objective_exact(const double* objpart, int32_t k, double* out,
+                                  hipStream_t s);
+// Row ids of mean-major means (for caller-given means).
+hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStream_t s);
+
+struct IvfArgs {
+    int64_t d, nnzM;
+    int32_t k, k_r, R, valtype;
+    const int32_t* mm_idx;
+    const double* mm_val;
+    const int32_t* mm_row;
+    uint32_t* keys;
+    uint32_t* vals;
+    uint32_t* keys_alt;
+    uint32_t* vals_alt;
+    const uint32_t* iota;
+    int64_t* ivf_ptr;    // [d + 1]
+    int64_t* sub_ptr;    // [d * (R + 1)]
+    int32_t* cid;        // [nnzM]
+    double* val64;       // [nnzM]
+    void* post;          // [nnzM] uint2 or uint32
+    void* tmp;
+};
+
+// Inverted-file rebuild: stable sort of the mean entries by term, then lists
+// in ascending cluster order with the stored-precision values.
+hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s);
+hipError_t launch_seed_assign(const int32_t* seeds, int32_t k, int64_t n, int32_t* assign,
+                              hipStream_t s);
+
+}  // namespace ivf

@@ -1,0 +1,237 @@
+// Device-wide exclusive scan and stable LSD radix sort of (uint32 key, uint32
+// value) pairs for gfx950.  Both are building blocks of the update step
+// (grouping object entries by cluster) and of the inverted-file transpose
+// (grouping mean entries by term), which need stable, deterministic orders.
+#include "ivf_internal.h"
+
+namespace ivf {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 16;
+constexpr int kTile = kBlock * kItems;      // 4096 items per block
+constexpr int kDigits = 256;
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+template <typename T>
+__device__ inline T wave_inclusive_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        T y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over the block; *total receives the block sum.
+template <typename T>
+__device__ inline T block_exclusive_scan(T x, T* sh, T* total) {
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    T inc = wave_inclusive_scan(x);
+    if (lane == kWave - 1) sh[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T acc = 0;
+        for (int i = 0; i < kBlock / kWave; ++i) {
+            T t = sh[i];
+            sh[i] = acc;
+            acc += t;
+        }
+        sh[kBlock / kWave] = acc;
+    }
+    __syncthreads();
+    T res = inc - x + sh[w];
+    *total = sh[kBlock / kWave];
+    __syncthreads();
+    return res;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tile_sums(const T* __restrict__ in, int64_t n,
+                                                      T* __restrict__ sums) {
+    __shared__ T sh[kBlock / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+        if (base + i < n) acc += in[base + i];
+    T total;
+    block_exclusive_scan(acc, sh, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_tile_scan(const T* __restrict__ in, T* __restrict__ out,
+                                                      int64_t n, const T* __restrict__ offs) {
+    __shared__ T sh[kBlock / kWave + 1];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    T v[kItems];
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : (T)0;
+        acc += v[i];
+    }
+    T total;
+    T run = block_exclusive_scan(acc, sh, &total);
+    if (offs) run += offs[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+}
+
+inline int64_t ntiles(int64_t n) { return (n + kTile - 1) / kTile; }
+
+template <typename T>
+size_t scan_levels_bytes(int64_t n) {
+    size_t b = 0;
+    while (n > kTile) {
+        n = ntiles(n);
+        b += ((size_t)n * sizeof(T) + 255) & ~(size_t)255;
+    }
+    return b;
+}
+
+template <typename T>
+hipError_t scan_impl(const T* in, T* out, int64_t n, void* tmp, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = ntiles(n);
+    if (nb == 1) {
+        k_tile_scan<T><<<1, kBlock, 0, s>>>(in, out, n, nullptr);
+        return hipGetLastError();
+    }
+    T* sums = reinterpret_cast<T*>(tmp);
+    void* rest = reinterpret_cast<char*>(tmp) + (((size_t)nb * sizeof(T) + 255) & ~(size_t)255);
+    k_tile_sums<T><<<(unsigned)nb, kBlock, 0, s>>>(in, n, sums);
+    hipError_t e = scan_impl<T>(sums, sums, nb, rest, s);
+    if (e != hipSuccess) return e;
+    k_tile_scan<T><<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, sums);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- radix sort
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
+                                                       int64_t n, int shift,
+                                                       uint32_t* __restrict__ hist,
+                                                       int64_t nt) {
+    __shared__ uint32_t h[kDigits];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + (int64_t)r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kDigits - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nt + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter: items are ranked in their input order (round, wave, lane).
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
+    const uint32_t* __restrict__ offs, int64_t nt, uint32_t* __restrict__ okeys,
+    uint32_t* __restrict__ ovals) {
+    constexpr int W = kBlock / kWave;
+    __shared__ uint32_t run[kDigits];
+    __shared__ uint32_t wcnt[W][kDigits];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    run[tid] = offs[(int64_t)tid * nt + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int r = 0; r < kItems; ++r) {
+        const int64_t i = base + (int64_t)r * kBlock + tid;
+        const bool valid = i < n;
+        uint32_t key = valid ? keys[i] : 0u;
+        uint32_t val = valid ? vals[i] : 0u;
+        const uint32_t d = (key >> shift) & (kDigits - 1);
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+#pragma unroll
+        for (int q = 0; q < W; ++q) wcnt[q][tid] = 0u;
+        __syncthreads();
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t acc = run[tid];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const uint32_t t = wcnt[q][tid];
+                wcnt[q][tid] = acc;
+                acc += t;
+            }
+            run[tid] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = wcnt[w][d] + rank;
+            okeys[pos] = key;
+            ovals[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) { return scan_levels_bytes<int64_t>(n) + 256; }
+
+hipError_t exclusive_scan_u32(const uint32_t* in, uint32_t* out, int64_t n, void* tmp,
+                              hipStream_t s) {
+    return scan_impl<uint32_t>(in, out, n, tmp, s);
+}
+
+hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp,
+                              hipStream_t s) {
+    return scan_impl<int64_t>(in, out, n, tmp, s);
+}
+
+size_t radix_tmp_bytes(int64_t n) {
+    const int64_t nt = ntiles(n > 0 ? n : 1);
+    const size_t hist = ((size_t)nt * kDigits * sizeof(uint32_t) + 255) & ~(size_t)255;
+    return hist + scan_levels_bytes<uint32_t>(nt * kDigits) + 256;
+}
+
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
+                            uint32_t* vals_alt, int64_t n, int bits, void* tmp, hipStream_t s,
+                            const uint32_t* vals_in_first) {
+    if (n <= 0) return hipSuccess;
+    if (bits < 1) bits = 1;
+    const int64_t nt = ntiles(n);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(tmp);
+    void* stmp = reinterpret_cast<char*>(tmp) +
+                 (((size_t)nt * kDigits * sizeof(uint32_t) + 255) & ~(size_t)255);
+    const int passes = (bits + 7) / 8;
+    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const uint32_t* vin = (p == 0 && vals_in_first) ? vals_in_first : vi;
+        k_radix_hist<<<(unsigned)nt, kBlock, 0, s>>>(ki, n, shift, hist, nt);
+        hipError_t e = scan_impl<uint32_t>(hist, hist, nt * kDigits, stmp, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<(unsigned)nt, kBlock, 0, s>>>(ki, vin, n, shift, hist, nt, ko, vo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint32_t* t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    if (ki != keys) {   // odd number of passes: move the result home
+        hipError_t e = hipMemcpyAsync(keys, ki, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(vals, vi, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace ivf

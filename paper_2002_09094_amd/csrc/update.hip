@@ -1,0 +1,554 @@
+// Update step of inverted-file spherical k-means (Algorithm 3, update part)
+// and the inverted-file rebuild, for gfx950.
+//
+// The object set's term-major view (entries ordered by (term, object), built
+// once) is stably radix-sorted by the entries' current cluster, which leaves
+// every cluster's entries grouped by term: each run of equal (cluster, term)
+// is one nonzero of the new mean.  Its member sum is accumulated in integer
+// fixed point with a per-term scale that holds every FP32 value of the term
+// exactly, so the sum is the exact real sum (independent of order and thread
+// count: a deterministic segmented reduction).  The mean is then the sum
+// divided by |C_j| and by the FP64 2-norm, as the paper orders the update.
+// Clusters without members keep their previous mean.
+//
+// The inverted-file rebuild stably sorts the new mean-major entries by term,
+// so every term's list comes out in ascending cluster order, the order the
+// paper's update loop produces.
+#include "ivf_internal.h"
+#include "kernels.h"
+
+namespace ivf {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int per_thread = 1) {
+    int64_t b = (n + (int64_t)kThreads * per_thread - 1) / ((int64_t)kThreads * per_thread);
+    return (unsigned)(b > 0 ? b : 1);
+}
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__global__ void k_validate_objects(ObjectView x, Counters* cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (x.x_ptr[0] != 0 || x.x_ptr[x.n] != x.nnz))
+        atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
+    if (i >= x.n) return;
+    const int64_t a = x.x_ptr[i], b = x.x_ptr[i + 1];
+    if (a < 0 || b < a || b > x.nnz) {
+        atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
+        return;
+    }
+    unsigned f = 0;
+    int32_t prevt = -1;
+    for (int64_t e = a; e < b; ++e) {
+        const int32_t t = x.x_idx[e];
+        const float v = x.x_val[e];
+        if (t < 0 || t >= x.d) f |= kBadIndex;
+        else if (t <= prevt) f |= kBadOrder;
+        prevt = t;
+        if (!isfinite(v)) f |= kNonFinite;
+        else if (!(v > 0.f)) f |= kNonPositive;
+    }
+    if (f) atomicOr(&cnt->error_flags, (unsigned long long)f);
+}
+
+__global__ void k_validate_means(const int64_t* ptr, const int32_t* idx, const double* val,
+                                 int32_t k, int64_t d, int64_t nnz, Counters* cnt) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j == 0 && (ptr[0] != 0 || ptr[k] != nnz))
+        atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
+    if (j >= k) return;
+    const int64_t a = ptr[j], b = ptr[j + 1];
+    if (a < 0 || b < a || b > nnz) {
+        atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
+        return;
+    }
+    unsigned f = 0;
+    int32_t prevt = -1;
+    for (int64_t e = a; e < b; ++e) {
+        const int32_t t = idx[e];
+        const double v = val[e];
+        if (t < 0 || t >= d) f |= kBadIndex;
+        else if (t <= prevt) f |= kBadOrder;
+        prevt = t;
+        if (!isfinite(v)) f |= kNonFinite;
+        else if (!(v > 0.0)) f |= kNonPositive;
+    }
+    if (f) atomicOr(&cnt->error_flags, (unsigned long long)f);
+}
+
+__global__ void k_row_ids(const int64_t* ptr, int64_t n, int32_t* rowid) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) rowid[e] = (int32_t)i;
+}
+
+__global__ void k_iota(uint32_t* out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (uint32_t)i;
+}
+
+__global__ void k_copy_keys(const int32_t* in, uint32_t* out, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (uint32_t)in[i];
+}
+
+__global__ void k_build_xt(const uint32_t* st, const uint32_t* sp, const int32_t* rowid,
+                           const float* x_val, int64_t nnz, int32_t* xt_obj, int32_t* xt_term,
+                           float* xt_val) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = sp[q];
+        xt_term[q] = (int32_t)st[q];
+        xt_obj[q] = rowid[e];
+        xt_val[q] = x_val[e];
+    }
+}
+
+__global__ void k_term_init(int32_t* emin, int32_t* emax, int32_t* count, int64_t d) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    emin[t] = 1 << 30;
+    emax[t] = -(1 << 30);
+    count[t] = 0;
+}
+
+__global__ void k_term_stats(const int32_t* x_idx, const float* x_val, int64_t nnz,
+                             int32_t* emin, int32_t* emax, int32_t* count) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t t = x_idx[e];
+        int32_t eb = (int32_t)((__float_as_uint(x_val[e]) >> 23) & 0xffu);
+        if (eb == 0) eb = 1;   // subnormals share the smallest normal exponent's lsb
+        atomicMin(&emin[t], eb);
+        atomicMax(&emax[t], eb);
+        atomicAdd(&count[t], 1);
+    }
+}
+
+__global__ void k_term_shift(const int32_t* emin, const int32_t* emax, const int32_t* count,
+                             int64_t d, int16_t* shift, Counters* cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    const int32_t c = count[t];
+    if (c == 0) {
+        shift[t] = 0;
+        return;
+    }
+    // lsb of the smallest value: every value of the term is an integer multiple
+    const int32_t s_exact = (emin[t] - 127) - 23;
+    const int32_t logc = c > 1 ? 32 - __clz((unsigned)(c - 1)) : 0;
+    // any member sum < c * 2^(emax + 1); keep it below 2^63 in lsb units
+    const int32_t need = logc + (emax[t] - 127 + 1) - s_exact;
+    int32_t s = s_exact;
+    if (need > 62) {
+        s += need - 62;
+        atomicAdd(&cnt->pad[0], 1ull);   // terms whose sums are rounded
+    }
+    shift[t] = (int16_t)s;
+}
+
+// ----------------------------------------------------------------- update
+__global__ void k_keys(const int32_t* __restrict__ xt_obj, const int32_t* __restrict__ assign,
+                       int64_t nnz, int32_t k, uint32_t* __restrict__ keys) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = assign[xt_obj[q]];
+        keys[q] = (a >= 0 && a < k) ? (uint32_t)a : (uint32_t)k;
+    }
+}
+
+__global__ void k_sizes(const int32_t* __restrict__ assign, int64_t n, int32_t k,
+                        int64_t* __restrict__ size) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = assign[i];
+        if (a >= 0 && a < k)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&size[a]), 1ull);
+    }
+}
+
+__global__ void k_zero_i64(int64_t* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_seg_flags(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                            const int32_t* __restrict__ xt_term, int64_t nnz, int32_t k,
+                            uint32_t* __restrict__ flag, int64_t* scal) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = keys[q];
+        const bool valid = key < (uint32_t)k;
+        uint32_t f = 0;
+        if (valid) {
+            if (q == 0) f = 1;
+            else {
+                const uint32_t kp = keys[q - 1];
+                f = (kp != key || xt_term[vals[q]] != xt_term[vals[q - 1]]) ? 1u : 0u;
+            }
+            if (q == nnz - 1 || keys[q + 1] >= (uint32_t)k) scal[0] = q + 1;
+        }
+        flag[q] = f;
+    }
+}
+
+__global__ void k_seg_count(const uint32_t* flag, const uint32_t* segpos, int64_t nnz,
+                            int64_t* scal) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        scal[1] = nnz > 0 ? (int64_t)segpos[nnz - 1] + flag[nnz - 1] : 0;
+}
+
+__global__ void k_zero_segs(unsigned long long* acc, const int64_t* scal, int64_t cap) {
+    const int64_t ns = scal[1];
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < ns && s < cap;
+         s += (int64_t)gridDim.x * blockDim.x)
+        acc[s] = 0ull;
+}
+
+__device__ inline unsigned long long to_fixed(float v, int sh) {
+    // exact when the term's scale holds v (the common case), else rounded to nearest
+    return (unsigned long long)llrint(ldexp((double)v, -sh));
+}
+
+constexpr int kRun = 8;
+
+__global__ void k_seg_sums(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                           const uint32_t* __restrict__ flag,
+                           const uint32_t* __restrict__ segpos,
+                           const int32_t* __restrict__ xt_term,
+                           const float* __restrict__ xt_val, const int16_t* __restrict__ shift,
+                           const int64_t* scal, unsigned long long* __restrict__ acc,
+                           int32_t* __restrict__ seg_j, int32_t* __restrict__ seg_t) {
+    const int64_t nv = scal[0];
+    const int64_t q0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRun;
+    if (q0 >= nv) return;
+    const int64_t q1 = min(nv, q0 + kRun);
+    int64_t cur = -1;
+    unsigned long long run = 0;
+    for (int64_t q = q0; q < q1; ++q) {
+        const uint32_t e = vals[q];
+        const int32_t t = xt_term[e];
+        const int64_t s = (int64_t)segpos[q] + flag[q] - 1;
+        if (flag[q]) {
+            seg_j[s] = (int32_t)keys[q];
+            seg_t[s] = t;
+        }
+        if (s != cur) {
+            if (cur >= 0) atomicAdd(&acc[cur], run);
+            cur = s;
+            run = 0;
+        }
+        run += to_fixed(xt_val[e], shift[t]);
+    }
+    if (cur >= 0) atomicAdd(&acc[cur], run);
+}
+
+__device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t lo, int64_t hi, int32_t x) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_cstart(const int32_t* seg_j, const int64_t* scal, int32_t k, int64_t* cstart) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > k) return;
+    cstart[j] = lower_bound_i32(seg_j, 0, scal[1], (int32_t)j);
+}
+
+__device__ inline double seg_value(const unsigned long long* acc, const int32_t* seg_t,
+                                   const int16_t* shift, int64_t s) {
+    return ldexp((double)acc[s], (int)shift[seg_t[s]]);
+}
+
+// One wave per cluster: FP64 norm of w = s / |C_j| (lane-strided partials,
+// then a fixed butterfly: deterministic), the cluster's share of the exact
+// objective mu_j(old) . s_j, and the new row length.
+__global__ __launch_bounds__(kThreads) void k_norms(UpdateArgs a) {
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = lane_id();
+    if (j >= a.k) return;
+    const int64_t nj = a.size[j];
+    if (nj == 0) {
+        if (lane == 0) {
+            a.newcnt[j] = a.old_ptr[j + 1] - a.old_ptr[j];
+            a.nrm[j] = 0.0;
+            a.objpart[j] = 0.0;
+            atomicAdd(&a.cnt->empty, 1ull);
+        }
+        return;
+    }
+    const int64_t s0 = a.cstart[j], s1 = a.cstart[j + 1];
+    const int64_t ob = a.old_ptr[j], oe = a.old_ptr[j + 1];
+    const double dn = (double)nj;
+    double ss = 0.0, op = 0.0;
+    for (int64_t s = s0 + lane; s < s1; s += kWave) {
+        const double sv = seg_value(a.seg_acc, a.seg_t, a.shift, s);
+        const double w = sv / dn;
+        ss += w * w;
+        const int32_t t = a.seg_t[s];
+        const int64_t p = lower_bound_i32(a.old_idx, ob, oe, t);
+        if (p < oe && a.old_idx[p] == t) op += a.old_val[p] * sv;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        ss += __shfl_xor(ss, o, kWave);
+        op += __shfl_xor(op, o, kWave);
+    }
+    if (lane == 0) {
+        a.nrm[j] = sqrt(ss);
+        a.objpart[j] = op;
+        a.newcnt[j] = s1 - s0;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(UpdateArgs a) {
+    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = lane_id();
+    if (j >= a.k) return;
+    const int64_t nj = a.size[j];
+    const int64_t p0 = a.new_ptr[j];
+    if (nj == 0) {
+        const int64_t ob = a.old_ptr[j], oe = a.old_ptr[j + 1];
+        for (int64_t e = ob + lane; e < oe; e += kWave) {
+            a.new_idx[p0 + (e - ob)] = a.old_idx[e];
+            a.new_val[p0 + (e - ob)] = a.old_val[e];
+            a.new_row[p0 + (e - ob)] = (int32_t)j;
+        }
+        return;
+    }
+    const int64_t s0 = a.cstart[j], s1 = a.cstart[j + 1];
+    const double dn = (double)nj, nr = a.nrm[j];
+    for (int64_t s = s0 + lane; s < s1; s += kWave) {
+        const double w = seg_value(a.seg_acc, a.seg_t, a.shift, s) / dn;
+        a.new_idx[p0 + (s - s0)] = a.seg_t[s];
+        a.new_val[p0 + (s - s0)] = w / nr;
+        a.new_row[p0 + (s - s0)] = (int32_t)j;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_k(const double* part, int32_t k, double* out) {
+    __shared__ double sh[kThreads];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < k; i += kThreads) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kThreads / 2; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_mean_rows(const int64_t* ptr, int32_t k, int32_t* row) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) row[e] = (int32_t)j;
+}
+
+// ----------------------------------------------------------- inverted file
+__device__ inline uint32_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __restrict__ mm_row,
+                           const double* __restrict__ mm_val, int64_t nnzM, int32_t k_r,
+                           int valtype, int32_t* __restrict__ cid, double* __restrict__ val64,
+                           void* __restrict__ post) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = vals[q];
+        const int32_t j = mm_row[p];
+        const double u = mm_val[p];
+        cid[q] = j;
+        val64[q] = u;
+        const float f = (float)u;
+        if (valtype == IVF_VAL_F32) {
+            reinterpret_cast<uint2*>(post)[q] = make_uint2((uint32_t)j, __float_as_uint(f));
+        } else {
+            const uint32_t local = (uint32_t)(j % k_r);
+            uint32_t h;
+            if (valtype == IVF_VAL_BF16) h = bf16_rne(f);
+            else h = (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)f);
+            reinterpret_cast<uint32_t*>(post)[q] = local | (h << 16);
+        }
+    }
+}
+
+__global__ void k_ivf_ptr(const uint32_t* skeys, int64_t nnzM, int64_t d, int64_t* ptr) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > d) return;
+    int64_t lo = 0, hi = nnzM;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (skeys[mid] < (uint32_t)t) lo = mid + 1; else hi = mid;
+    }
+    ptr[t] = lo;
+}
+
+__global__ void k_sub_ptr(const int64_t* ptr, const int32_t* cid, int64_t d, int32_t R,
+                          int32_t k_r, int64_t* sub) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d) return;
+    const int64_t a = ptr[t], b = ptr[t + 1];
+    int64_t lo = a;
+    for (int32_t r = 0; r < R; ++r) {
+        lo = lower_bound_i32(cid, lo, b, r * k_r);
+        sub[t * (R + 1) + r] = lo;
+    }
+    sub[t * (R + 1) + R] = b;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_scatter_seeds(const int32_t* seeds, int32_t k, int64_t n, int32_t* assign) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    const int32_t i = seeds[j];
+    if (i >= 0 && i < n) assign[i] = (int32_t)j;
+}
+
+inline int bits_for(int64_t maxval) {
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) <= maxval) ++b;
+    return b;
+}
+
+inline unsigned capped(int64_t n) {
+    const int64_t b = (n + kThreads - 1) / kThreads;
+    return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
+}
+
+#define HIP_RET(x)                           \
+    do {                                     \
+        hipError_t e_ = (x);                 \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+}  // namespace
+
+hipError_t launch_validate_objects(const ObjectView& x, Counters* cnt, hipStream_t s) {
+    k_validate_objects<<<grid_for(x.n + 1), kThreads, 0, s>>>(x, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_means(const int64_t* ptr, const int32_t* idx, const double* val,
+                                 int32_t k, int64_t d, int64_t nnz, Counters* cnt,
+                                 hipStream_t s) {
+    k_validate_means<<<grid_for(k + 1), kThreads, 0, s>>>(ptr, idx, val, k, d, nnz, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_ids(const int64_t* ptr, int64_t n, int32_t* rowid, hipStream_t s) {
+    k_row_ids<<<grid_for(n), kThreads, 0, s>>>(ptr, n, rowid);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s) {
+    k_iota<<<capped(n), kThreads, 0, s>>>(out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_keys(const int32_t* in, uint32_t* out, int64_t n, hipStream_t s) {
+    k_copy_keys<<<capped(n), kThreads, 0, s>>>(in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_xt(const uint32_t* st, const uint32_t* sp, const int32_t* rowid,
+                           const float* x_val, int64_t nnz, int32_t* xt_obj, int32_t* xt_term,
+                           float* xt_val, hipStream_t s) {
+    k_build_xt<<<capped(nnz), kThreads, 0, s>>>(st, sp, rowid, x_val, nnz, xt_obj, xt_term,
+                                                 xt_val);
+    return hipGetLastError();
+}
+
+hipError_t launch_term_shift(const int32_t* x_idx, const float* x_val, int64_t nnz, int64_t d,
+                             int32_t* emin, int32_t* emax, int32_t* count, int16_t* shift,
+                             Counters* cnt, hipStream_t s) {
+    k_term_init<<<grid_for(d), kThreads, 0, s>>>(emin, emax, count, d);
+    k_term_stats<<<capped(nnz), kThreads, 0, s>>>(x_idx, x_val, nnz, emin, emax, count);
+    k_term_shift<<<grid_for(d), kThreads, 0, s>>>(emin, emax, count, d, shift, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s) {
+    const int64_t nnz = a.nnz;
+    k_zero_i64<<<capped(a.k + 1), kThreads, 0, s>>>(a.size, a.k);
+    k_zero_i64<<<1, kThreads, 0, s>>>(a.scal, 4);
+    k_sizes<<<capped(a.n), kThreads, 0, s>>>(a.assign, a.n, a.k, a.size);
+    HIP_RET(hipGetLastError());
+    if (nnz > 0) {
+        k_keys<<<capped(nnz), kThreads, 0, s>>>(a.xt_obj, a.assign, nnz, a.k, a.keys);
+        HIP_RET(hipGetLastError());
+        HIP_RET(radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, nnz, bits_for(a.k),
+                                 a.tmp, s, a.iota));
+        k_seg_flags<<<capped(nnz), kThreads, 0, s>>>(a.keys, a.vals, a.xt_term, nnz, a.k, a.flag,
+                                                     a.scal);
+        HIP_RET(hipGetLastError());
+        HIP_RET(exclusive_scan_u32(a.flag, a.segpos, nnz, a.tmp, s));
+        k_seg_count<<<1, 64, 0, s>>>(a.flag, a.segpos, nnz, a.scal);
+        k_zero_segs<<<capped(nnz), kThreads, 0, s>>>(a.seg_acc, a.scal, nnz);
+        k_seg_sums<<<grid_for(nnz, kRun), kThreads, 0, s>>>(a.keys, a.vals, a.flag, a.segpos,
+                                                            a.xt_term, a.xt_val, a.shift, a.scal,
+                                                            a.seg_acc, a.seg_j, a.seg_t);
+        HIP_RET(hipGetLastError());
+    }
+    k_cstart<<<grid_for(a.k + 1), kThreads, 0, s>>>(a.seg_j, a.scal, a.k, a.cstart);
+    k_norms<<<grid_for((int64_t)a.k * kWave), kThreads, 0, s>>>(a);
+    HIP_RET(hipGetLastError());
+    // new row pointers: exclusive scan of k + 1 counts (the last is 0)
+    k_zero_i64<<<1, 64, 0, s>>>(a.newcnt + a.k, 1);
+    HIP_RET(exclusive_scan_i64(a.newcnt, a.new_ptr, (int64_t)a.k + 1, a.tmp, s));
+    return hipGetLastError();
+}
+
+hipError_t launch_update_fill(UpdateArgs& a, hipStream_t s) {
+    k_fill<<<grid_for((int64_t)a.k * kWave), kThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_objective_exact(const double* objpart, int32_t k, double* out,
+                                  hipStream_t s) {
+    k_sum_k<<<1, kThreads, 0, s>>>(objpart, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStream_t s) {
+    k_mean_rows<<<grid_for(k), kThreads, 0, s>>>(ptr, k, row);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
+    if (a.nnzM > 0) {
+        k_copy_keys<<<capped(a.nnzM), kThreads, 0, s>>>(a.mm_idx, a.keys, a.nnzM);
+        HIP_RET(hipGetLastError());
+        HIP_RET(radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.nnzM,
+                                 bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, a.iota));
+        k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM, a.k_r,
+                                                       a.valtype, a.cid, a.val64, a.post);
+        HIP_RET(hipGetLastError());
+    }
+    k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.d, a.ivf_ptr);
+    k_sub_ptr<<<grid_for(a.d), kThreads, 0, s>>>(a.ivf_ptr, a.cid, a.d, a.R, a.k_r, a.sub_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_assign(const int32_t* seeds, int32_t k, int64_t n, int32_t* assign,
+                              hipStream_t s) {
+    k_fill_i32<<<capped(n), kThreads, 0, s>>>(assign, n, -1);
+    k_scatter_seeds<<<grid_for(k), kThreads, 0, s>>>(seeds, k, n, assign);
+    return hipGetLastError();
+}
+
+}  // namespace ivf

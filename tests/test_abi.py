@@ -1,0 +1,129 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol the header
+declares, and its host-only entry points (planner, certification constants,
+argument checks that precede any launch) behave as documented."""
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import paper_2002_09094_amd as ivf
+from paper_2002_09094_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ivf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ivf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding wraps exactly the declared set
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_status_strings_and_defaults():
+    lib = _lib.get()
+    assert lib.ivf_status_str(0) == b"IVF_OK"
+    assert lib.ivf_status_str(-2) == b"IVF_ERR_UNSORTED"
+    o = _lib.ivf_options()
+    lib.ivf_default_options(ctypes.byref(o))
+    assert o.valtype == 0 and o.certify == 1 and o.cluster_range == 0
+
+
+def test_planner():
+    p = ivf.plan_shape(100)
+    assert p["ranges"] == 1 and p["k_r"] == 100
+    p = ivf.plan_shape(10_000)
+    assert p["ranges"] * p["k_r"] >= 10_000 and p["k_r"] <= 4096
+    assert p["lds_bytes"] <= 160 * 1024
+    p = ivf.plan_shape(50_000)
+    assert p["ranges"] >= 13 and p["ranges64"] == 7
+    p = ivf.plan_shape(1000, cluster_range=64)
+    assert p["k_r"] <= 64 and p["ranges"] == 16
+    with pytest.raises(ivf.IvfError):
+        ivf.plan_shape(0)
+    with pytest.raises(ivf.IvfError):
+        ivf.plan_shape(100, waves_per_wg=17)
+
+
+def test_build_rejects_bad_arguments_before_any_launch():
+    lib = _lib.get()
+    h = ctypes.c_void_p()
+    # null object set
+    assert lib.ivf_build(None, 3, None, ctypes.byref(h)) == -1
+    x = _lib.ivf_csr(10, 5, 20, 1, 1, 1)   # dummy non-null pointers, never read
+    assert lib.ivf_build(ctypes.byref(x), 11, None, ctypes.byref(h)) == -1   # k > n
+    assert lib.ivf_build(ctypes.byref(x), 0, None, ctypes.byref(h)) == -1    # k < 1
+    big = _lib.ivf_csr(10, 5, 1 << 31, 1, 1, 1)
+    assert lib.ivf_build(ctypes.byref(big), 3, None, ctypes.byref(h)) == -5  # capacity
+    o = _lib.ivf_options()
+    lib.ivf_default_options(ctypes.byref(o))
+    o.valtype = 7
+    assert lib.ivf_build(ctypes.byref(x), 3, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert b"valtype" in lib.ivf_last_error(None)
+    assert h.value is None
+
+
+def _exact_gamma(n, u):
+    return Fraction(n) * u / (1 - Fraction(n) * u)
+
+
+@pytest.mark.parametrize("vt,us", [("f32", Fraction(1, 2 ** 24)),
+                                   ("bf16", Fraction(1, 2 ** 8) + Fraction(1, 2 ** 24) +
+                                    Fraction(1, 2 ** 32)),
+                                   ("f16", Fraction(1, 2 ** 11) + Fraction(1, 2 ** 24) +
+                                    Fraction(1, 2 ** 35))])
+@pytest.mark.parametrize("nt", [1, 60, 2000])
+def test_cert_constants_follow_recursive_summation_bound(vt, us, nt):
+    c, a, g = ivf.cert_bound(vt, nt)
+    u32 = Fraction(1, 2 ** 24)
+    want = (1 + us) * (1 + _exact_gamma(nt, u32)) - 1
+    assert c >= float(want) * 1.01 and c <= float(want) * 1.0101 + 1e-14
+    assert g >= float(_exact_gamma(nt, Fraction(1, 2 ** 53)))
+    assert (a > 0) == (vt == "f16")
+
+
+def _round_bf16(x32):
+    b = x32.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("vt", ["f32", "bf16", "f16"])
+def test_cert_bound_holds_for_emulated_fp32_scores(vt):
+    """Emulate the tile arithmetic on the CPU (mean value rounded to the stored
+    precision, FP32 product, sequential FP32 sum) and check the stated bound
+    against the exact score, including adversarial magnitudes."""
+    rng = np.random.default_rng(3)
+    for trial in range(300):
+        nt = int(rng.integers(1, 400))
+        v = rng.uniform(0, 1, nt) ** rng.uniform(1, 8)
+        v = (v / np.linalg.norm(v)).astype(np.float32)
+        v[v == 0] = np.float32(1e-30)
+        u = (rng.uniform(0, 1, nt) ** rng.uniform(1, 12)) * 10.0 ** -rng.uniform(0, 6)
+        u = u.astype(np.float64)
+        u32 = u.astype(np.float32)
+        if vt == "bf16":
+            us = _round_bf16(u32)
+        elif vt == "f16":
+            us = u32.astype(np.float16).astype(np.float32)
+        else:
+            us = u32
+        acc = np.float32(0)
+        for t in range(nt):
+            acc = np.float32(acc + np.float32(v[t] * us[t]))
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
+        c, a, _ = ivf.cert_bound(vt, nt)
+        err = abs(Fraction(float(acc)) - exact)
+        assert err <= Fraction(c) * exact + Fraction(a), (vt, trial, float(err), float(exact))

@@ -1,0 +1,237 @@
+"""Benchmark: Lloyd iterations of inverted-file spherical k-means on one MI355X.
+
+One step = one whole Lloyd iteration (assignment walk + certification + FP64
+re-scores + objective, then the update: exact member sums, FP64 norms and the
+inverted-file rebuild) over the full synthetic object set, which is resident
+in HBM before the timed region starts.
+
+Default workload: 8,000,000 synthetic Zipf tf-idf documents over 140,000 terms
+(Poisson(60) nonzeros clipped to [3, 1000], Zipf s = 1.1), k = 10,000, FP32
+inverted-file values.  Prints ONE JSON line on stdout; progress goes to stderr.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Lloyd iter/s and sparse mult-adds/s at 8M docs×140k terms, k=10k; HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+COPY_BYTES = 1 << 30
+ENTRY_BYTES = {"f32": 8, "bf16": 4, "f16": 4}   # (cluster id, value) per posting entry
+
+
+def log(msg):
+    print("[bench %7.1fs] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
+
+
+T0 = time.perf_counter()
+
+
+def walk_bytes(m, nnz, n, valtype):
+    """Algorithmic bytes of one walk launch: every posting entry walked (cluster
+    id + value), each object nonzero (term id + value) with its list bounds
+    (two int32), the object row pointers."""
+    return ENTRY_BYTES[valtype] * m + 16 * nnz + 8 * (n + 1)
+
+
+def iteration_bytes(m, nnz, n, nnz_means, valtype):
+    """Algorithmic bytes of one Lloyd iteration: the walk, the assignment
+    read/write, and the update (the object entries grouped by cluster: key,
+    position, term, value; FP64 mean entries written; inverted file written)."""
+    return (walk_bytes(m, nnz, n, valtype) + 8 * n + 16 * nnz
+            + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("assign.hip", "kernels.h", "ivf_internal.h"):
+        with open(os.path.join(ROOT, "paper_2002_09094_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, valtype, n_launch_units):
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "walk_%s_%s_traffic.json" % (workload, valtype))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x, k, seed, target_s):
+    """The FP64 oracle timed on this host's cores on a bounded sample: means of a
+    seeded random partition (the shape of steady-state means on structureless
+    data), the assignment walk of the first S objects, scaled to the full set
+    by the exact mult-add count."""
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    labels = datagen.uniform_labels(x.n, k, seed, stream=11)
+    log("cpu baseline: oracle update of a random partition (k=%d)" % k)
+    means, _ = oracle.update(x, k, labels, None, threads=threads)
+    no, nc = oracle.term_counts(x, means)
+    m_full = int(np.sum(no * nc))
+    s = min(x.n, 2000)
+    while True:
+        xs = x.subset(np.arange(s))
+        t = time.perf_counter()
+        r = oracle.assign(xs, means, np.full(s, -1, np.int32), threads=threads)
+        dt = time.perf_counter() - t
+        log("cpu baseline: %d objects, %.3e mult-adds in %.2fs" % (s, r.mult_adds, dt))
+        if dt >= 0.5 * target_s or s >= x.n:
+            break
+        s = int(min(x.n, max(2 * s, s * target_s / max(dt, 1e-3))))
+    rate = r.mult_adds / dt
+    return {
+        "value": rate / m_full,
+        "unit": "iter/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": ("FP64 oracle assignment walk of the first %d of %d objects against "
+                   "means of a seeded random partition (k=%d), %.1fs; scaled by the full "
+                   "set's exact mult-add count %d" % (s, x.n, k, dt, m_full)),
+        "mult_adds_per_s": rate,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="pubmed_8m")
+    ap.add_argument("--valtype", default="f32", choices=sorted(ENTRY_BYTES))
+    ap.add_argument("--cluster-range", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy 3 times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2002_09094_amd as ivf
+
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x %d bytes" % COPY_BYTES)
+    w = datagen.WORKLOADS[args.workload]
+    log("generating %s: n=%d d=%d lambda=%g k=%d" % (w.name, w.n, w.d, w.lam, w.k))
+    x = w.generate()
+    seeds = w.seeds(x)
+    log("generated nnz=%d" % x.nnz)
+    dev = "cuda:0"
+    xd = (torch.from_numpy(x.indptr).to(dev), torch.from_numpy(x.indices).to(dev),
+          torch.from_numpy(x.values).to(dev))
+    km = ivf.IVFKMeans(*xd, w.d, w.k, valtype=args.valtype, cluster_range=args.cluster_range,
+                       waves_per_wg=args.waves, objects_per_item=args.chunk)
+    km.init_seeds(torch.from_numpy(seeds.astype(np.int32)).to(dev))
+    a = torch.full((w.n,), -1, dtype=torch.int32, device=dev)
+    log("built; plan %s" % km.plan)
+    for r in range(args.warmup):
+        sa = km.assign(a)
+        su = km.update(a)
+        log("warmup %d: assign %.1f ms (walk %.1f), update %.1f ms, M=%.3e, rescored=%d"
+            % (r, sa["assign_ms"], sa["walk_ms"], su["update_ms"], sa["mult_adds"],
+               sa["rescored"]))
+    torch.cuda.synchronize()
+    per = []
+    t_start = time.perf_counter()
+    for r in range(args.steps):
+        sa = km.assign(a)
+        su = km.update(a)
+        per.append((sa, su))
+        log("step %d: assign %.1f ms (walk %.1f), update %.1f ms, M=%.3e, certified=%d, "
+            "rescored=%d, changed=%d" % (r, sa["assign_ms"], sa["walk_ms"], su["update_ms"],
+                                         sa["mult_adds"], sa["certified"], sa["rescored"],
+                                         sa["changed"]))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+
+    mult = sum(p[0]["mult_adds"] for p in per)
+    walk_s = sum(p[0]["walk_ms"] for p in per) / 1e3
+    assign_s = sum(p[0]["assign_ms"] for p in per) / 1e3
+    bytes_iter = sum(iteration_bytes(p[0]["mult_adds"], x.nnz, x.n, p[1]["nnz_means"],
+                                     args.valtype) for p in per)
+    wb = [walk_bytes(p[0]["mult_adds"], x.nnz, x.n, args.valtype) for p in per]
+    walk_avg_s = walk_s / len(per)
+    achieved = (sum(wb) / len(wb)) / walk_avg_s / 1e9
+    traffic = measured_traffic(w.name, args.valtype, None)
+    out = {
+        "metric": METRIC,
+        "value": args.steps / t_total,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.valtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k, "nnz": x.nnz,
+                   "lambda": w.lam, "zipf_s": w.s, "seed": w.seed, "valtype": args.valtype,
+                   "plan": km.plan},
+        "mult_adds_per_s": mult / t_total,
+        "mult_adds_per_s_walk": mult / walk_s,
+        "mult_adds_per_iter": mult / len(per),
+        "hbm_gbps_algorithmic": bytes_iter / t_total / 1e9,
+        "assign_ms": 1e3 * assign_s / len(per),
+        "walk_ms": 1e3 * walk_avg_s,
+        "update_ms": sum(p[1]["update_ms"] for p in per) / len(per),
+        "certified_fraction": sum(p[0]["certified"] for p in per) / (len(per) * x.n),
+        "rescored_per_iter": sum(p[0]["rescored"] for p in per) / len(per),
+        "max_rel_err": max(p[0]["max_rel_err"] for p in per),
+        "objective": per[-1][1]["objective_exact"],
+        "roofline": {
+            "kernel": "k_walk",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+        },
+    }
+    km.close()
+    del xd
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x, w.k, w.seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

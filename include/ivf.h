@@ -109,6 +109,7 @@ typedef struct {
     int64_t mult_adds;       /* M = sum_i sum_h (nc)_{t(i,h)} (the paper's Eq. ivf_mult) */
     double max_rel_err;      /* max |rho~ - rho64| / rho64 over re-scored objects' winners */
     float assign_ms;         /* device time of the assignment step */
+    float walk_ms;           /* device time of its inverted-file walk kernel alone */
     /* update step */
     double objective_exact;  /* sum_j mu_j(old) . s_j(new member sum), FP64: the same J
                                 as `objective` computed from the update's exact sums */

@@ -41,6 +41,7 @@ class ivf_stats(ctypes.Structure):
     _fields_ = [("objective", c_double), ("objective_bound", c_double), ("changed", c_int64),
                 ("certified", c_int64), ("rescored", c_int64), ("zero_overlap", c_int64),
                 ("mult_adds", c_int64), ("max_rel_err", c_double), ("assign_ms", c_float),
+                ("walk_ms", c_float),
                 ("objective_exact", c_double), ("empty_clusters", c_int64),
                 ("nnz_means", c_int64), ("inexact_terms", c_int64), ("update_ms", c_float)]
 

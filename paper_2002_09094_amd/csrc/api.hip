@@ -73,7 +73,7 @@ struct ivf_handle {
     double* part = nullptr;
     double* dscal = nullptr;   // [0] objective, [1] exact objective
     Counters* cnt = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::string err;
 };
 
@@ -578,7 +578,9 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
     w.k = h->k; w.k_r = p.k_r; w.R = p.R; w.chunk = p.chunk; w.tile_stride = p.tile_stride;
     w.items_per_range = (h->n + p.chunk - 1) / p.chunk;
     w.cnt = h->cnt; w.rec = h->rec;
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[4], s));
     HIPCHK(h, launch_walk(w, h->opt.valtype, p.waves, p.lds_bytes, h->walk_grid, s));
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[5], s));
     MergeArgs m{};
     m.x_ptr = h->x_ptr; m.n = h->n; m.R = p.R;
     m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
@@ -606,6 +608,8 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
         HIPCHK(h, hipMemcpy(&obj, h->dscal, sizeof(obj), hipMemcpyDeviceToHost));
         float ms = 0.f;
         HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+        float wms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&wms, h->ev[4], h->ev[5]));
         double bound, err;
         std::memcpy(&bound, &c.max_bound_bits, sizeof(double));
         std::memcpy(&err, &c.max_err_bits, sizeof(double));
@@ -618,6 +622,7 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
         stats->mult_adds = (int64_t)c.mult;
         stats->max_rel_err = err;
         stats->assign_ms = ms;
+        stats->walk_ms = wms;
         stats->objective_exact = std::nan("");
         stats->empty_clusters = -1;
         stats->nnz_means = h->nnzM;

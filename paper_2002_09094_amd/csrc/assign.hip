@@ -3,7 +3,7 @@
 //
 //   k_walk     For each (cluster range, object): stream the object's CSR
 //              nonzeros, gather the range's slice of each term's posting list
-//              and scatter-accumulate x_t * m_jt into a per-wave FP32 LDS score
+//              and accumulate x_t * m_jt into a per-wave FP32 LDS score
 //              tile (one wave owns one tile, so every slot is accumulated in
 //              ascending term order); a fused wave-wide pass then extracts the
 //              range's top-1 (lowest id on equal scores) and top-2 and clears
@@ -32,51 +32,71 @@ __device__ inline float rlf(float x, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
-__device__ inline void lds_add(float* p, float v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 __device__ inline float widen16(uint32_t bits16, int vt) {
     if (vt == IVF_VAL_BF16) return __uint_as_float(bits16 << 16);
     return (float)__builtin_bit_cast(_Float16, (unsigned short)bits16);
 }
 
-// One term's posting slice [qb, qe) scattered into the tile (F32 entries).
-__device__ inline void walk_f32(const uint2* __restrict__ P, int64_t qb, int64_t qe, float v,
-                                float* tile, int32_t base, int lane) {
-    for (int64_t q0 = qb; q0 < qe; q0 += 4 * kWave) {
-        const int64_t q = q0 + lane;
-        const bool b0 = q < qe, b1 = q + kWave < qe, b2 = q + 2 * kWave < qe,
-                   b3 = q + 3 * kWave < qe;
-        uint2 e0 = make_uint2(0, 0), e1 = e0, e2 = e0, e3 = e0;
-        if (b0) e0 = P[q];
-        if (b1) e1 = P[q + kWave];
-        if (b2) e2 = P[q + 2 * kWave];
-        if (b3) e3 = P[q + 3 * kWave];
-        if (b0) lds_add(tile + ((int32_t)e0.x - base), v * __uint_as_float(e0.y));
-        if (b1) lds_add(tile + ((int32_t)e1.x - base), v * __uint_as_float(e1.y));
-        if (b2) lds_add(tile + ((int32_t)e2.x - base), v * __uint_as_float(e2.y));
-        if (b3) lds_add(tile + ((int32_t)e3.x - base), v * __uint_as_float(e3.y));
-    }
-}
+// Posting entries: F32 = {cluster id, value bits}; 16-bit values = local
+// cluster id (low half) | value bits (high half).
+template <int VT> struct Entry;
+template <> struct Entry<IVF_VAL_F32> {
+    using T = uint2;
+    __device__ static int32_t slot(T e, int32_t base) { return (int32_t)e.x - base; }
+    __device__ static float value(T e) { return __uint_as_float(e.y); }
+};
+template <int VT> struct Entry16 {
+    using T = uint32_t;
+    __device__ static int32_t slot(T e, int32_t) { return (int32_t)(e & 0xffffu); }
+    __device__ static float value(T e) { return widen16(e >> 16, VT); }
+};
+template <> struct Entry<IVF_VAL_BF16> : Entry16<IVF_VAL_BF16> {};
+template <> struct Entry<IVF_VAL_F16> : Entry16<IVF_VAL_F16> {};
 
-// 16-bit values: entry = local cluster id (low 16 bits) | value bits (high 16).
+constexpr int kUnroll = 8;
+
+// One term's posting slice [qb, qe) accumulated into the wave's own tile:
+// tile[c] = tile[c] + v * u for every entry (c, u).  LDS float atomics are
+// slow on this part and not needed: the tile belongs to this wave alone, and
+// one term's list names every cluster at most once, so all reads of a batch
+// may be issued before its writes.  Slots are updated in ascending term order.
 template <int VT>
-__device__ inline void walk_h16(const uint32_t* __restrict__ P, int64_t qb, int64_t qe, float v,
-                                float* tile, int lane) {
-    for (int64_t q0 = qb; q0 < qe; q0 += 4 * kWave) {
-        const int64_t q = q0 + lane;
-        const bool b0 = q < qe, b1 = q + kWave < qe, b2 = q + 2 * kWave < qe,
-                   b3 = q + 3 * kWave < qe;
-        uint32_t e0 = 0, e1 = 0, e2 = 0, e3 = 0;
-        if (b0) e0 = P[q];
-        if (b1) e1 = P[q + kWave];
-        if (b2) e2 = P[q + 2 * kWave];
-        if (b3) e3 = P[q + 3 * kWave];
-        if (b0) lds_add(tile + (e0 & 0xffffu), v * widen16(e0 >> 16, VT));
-        if (b1) lds_add(tile + (e1 & 0xffffu), v * widen16(e1 >> 16, VT));
-        if (b2) lds_add(tile + (e2 & 0xffffu), v * widen16(e2 >> 16, VT));
-        if (b3) lds_add(tile + (e3 & 0xffffu), v * widen16(e3 >> 16, VT));
+__device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, int64_t qb,
+                                  int64_t qe, float v, float* tile, int32_t base, int lane) {
+    using E = Entry<VT>;
+    int64_t q0 = qb;
+    for (; q0 + kUnroll * kWave <= qe; q0 += kUnroll * kWave) {
+        typename E::T e[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) e[u] = P[q0 + u * kWave + lane];
+        float r[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) r[u] = tile[E::slot(e[u], base)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const float p = v * E::value(e[u]);
+            tile[E::slot(e[u], base)] = r[u] + p;
+        }
+    }
+    if (q0 < qe) {   // the last, partial batch: fewer than kUnroll * 64 entries
+        typename E::T e[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t q = q0 + u * kWave + lane;
+            ok[u] = q < qe;
+            if (ok[u]) e[u] = P[q];
+        }
+        float r[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (ok[u]) r[u] = tile[E::slot(e[u], base)];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (ok[u]) {
+                const float p = v * E::value(e[u]);
+                tile[E::slot(e[u], base)] = r[u] + p;
+            }
     }
 }
 
@@ -135,12 +155,8 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_walk(WalkArgs a) {
                     const int64_t qb = rl64(pb, hh), qe = rl64(pe, hh);
                     const float vv = rlf(v, hh);
                     m += (int32_t)(qe - qb);
-                    if (VT == IVF_VAL_F32)
-                        walk_f32(reinterpret_cast<const uint2*>(a.post), qb, qe, vv, tile, base,
-                                 lane);
-                    else
-                        walk_h16<VT>(reinterpret_cast<const uint32_t*>(a.post), qb, qe, vv, tile,
-                                     lane);
+                    walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), qb,
+                                   qe, vv, tile, base, lane);
                 }
             }
             // fused top-2 over the tile, clearing it for the next object

@@ -112,7 +112,61 @@ def cpu_baseline(x, k, seed, target_s):
     }
 
 
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def summarize_trace(stats_csv, out_txt, command):
+    """Text summary of a rocprofv3 --kernel-trace --stats run."""
+    rows = _csv_rows(stats_csv)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel statistics", "# command: " + command, "",
+             "%-40s %6s %14s %14s %7s" % ("kernel", "calls", "total_ms", "avg_ms", "pct")]
+    for r in rows[:25]:
+        name = r["Name"].replace("ivf::(anonymous namespace)::", "").split("(")[0]
+        lines.append("%-40s %6s %14.3f %14.3f %7.2f" % (
+            name[:40], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+            float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, command):
+    """HBM traffic of the last walk launch from FETCH_SIZE and WRITE_SIZE runs
+    (KiB per dispatch), each scaled so that the calibration copy of COPY_BYTES
+    reads and writes exactly COPY_BYTES."""
+    def pick(path, counter):
+        rows = [r for r in _csv_rows(path) if r["Counter_Name"] == counter]
+        copies = [float(r["Counter_Value"]) for r in rows
+                  if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1e5][:3]
+        walks = [r for r in rows if "k_walk" in r["Kernel_Name"]]
+        return copies, walks
+    fc, fw = pick(fetch_csv, "FETCH_SIZE")
+    wc, ww = pick(write_csv, "WRITE_SIZE")
+    f_scale = COPY_BYTES / (1024.0 * sum(fc) / len(fc))
+    w_scale = COPY_BYTES / (1024.0 * sum(wc) / len(wc))
+    fetch = float(fw[-1]["Counter_Value"]) * 1024.0 * f_scale
+    write = float(ww[-1]["Counter_Value"]) * 1024.0 * w_scale
+    out = {"kernel": "k_walk", "workload": workload, "valtype": valtype,
+           "kernel_hash": kernel_hash(), "fetch_bytes": fetch, "write_bytes": write,
+           "hbm_bytes_per_launch": fetch + write, "fetch_scale": f_scale,
+           "write_scale": w_scale, "copy_fetch_kib": fc, "copy_write_kib": wc,
+           "walk_fetch_kib_raw": float(fw[-1]["Counter_Value"]),
+           "walk_write_kib_raw": float(ww[-1]["Counter_Value"]), "command": command}
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
+        summarize_trace(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
+        print(json.dumps(summarize_counters(*sys.argv[2:8])))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -188,6 +242,7 @@ def main():
     walk_avg_s = walk_s / len(per)
     achieved = (sum(wb) / len(wb)) / walk_avg_s / 1e9
     traffic = measured_traffic(w.name, args.valtype, None)
+    traffic_gbps = traffic / walk_avg_s / 1e9 if traffic else None
     out = {
         "metric": METRIC,
         "value": args.steps / t_total,
@@ -223,6 +278,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": traffic,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+            "traffic_gbps": traffic_gbps,
+            "traffic_frac": traffic_gbps / HBM_PEAK_GBPS if traffic_gbps else None,
         },
     }
     km.close()

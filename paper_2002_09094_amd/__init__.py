@@ -37,7 +37,7 @@ def _need_cuda(t, dtype, name):
 
 
 def _options(valtype="f32", certify=True, cluster_range=0, waves_per_wg=0, objects_per_item=0,
-             force_rescore=False, stream=None):
+             force_rescore=False, dense_threshold=0.0, stream=None):
     o = _lib.ivf_options()
     _lib.get().ivf_default_options(ctypes.byref(o))
     o.valtype = VALTYPES[valtype] if isinstance(valtype, str) else int(valtype)
@@ -46,6 +46,7 @@ def _options(valtype="f32", certify=True, cluster_range=0, waves_per_wg=0, objec
     o.waves_per_wg = int(waves_per_wg)
     o.objects_per_item = int(objects_per_item)
     o.force_rescore = 1 if force_rescore else 0
+    o.dense_threshold = float(dense_threshold)
     o.stream = ctypes.c_void_p(stream) if stream else None
     return o
 
@@ -77,7 +78,7 @@ class IVFKMeans:
 
     def __init__(self, indptr, indices, values, d, k, *, valtype="f32", certify=True,
                  cluster_range=0, waves_per_wg=0, objects_per_item=0, force_rescore=False,
-                 stream=None):
+                 dense_threshold=0.0, stream=None):
         import torch
         _need_cuda(indptr, torch.int64, "indptr")
         _need_cuda(indices, torch.int32, "indices")
@@ -91,7 +92,7 @@ class IVFKMeans:
         self.nnz = indices.numel()
         x = _lib.ivf_csr(self.n, self.d, self.nnz, _ptr(indptr), _ptr(indices), _ptr(values))
         o = _options(valtype, certify, cluster_range, waves_per_wg, objects_per_item,
-                     force_rescore, stream)
+                     force_rescore, dense_threshold, stream)
         h = ctypes.c_void_p()
         check(_lib.get().ivf_build(ctypes.byref(x), self.k, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

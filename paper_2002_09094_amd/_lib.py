@@ -34,7 +34,8 @@ class ivf_means(ctypes.Structure):
 class ivf_options(ctypes.Structure):
     _fields_ = [("valtype", c_int32), ("certify", c_int32), ("cluster_range", c_int32),
                 ("waves_per_wg", c_int32), ("objects_per_item", c_int32),
-                ("force_rescore", c_int32), ("stream", c_void_p)]
+                ("force_rescore", c_int32), ("dense_threshold", c_float),
+                ("stream", c_void_p)]
 
 
 class ivf_stats(ctypes.Structure):

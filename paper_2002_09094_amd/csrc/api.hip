@@ -57,7 +57,11 @@ struct ivf_handle {
     // inverted file
     int64_t ivf_cap = 0;
     int64_t* ivf_ptr = nullptr;
-    int64_t* sub_ptr = nullptr;
+    SliceDesc* desc = nullptr;
+    int64_t* dsz = nullptr;
+    void* slab = nullptr;
+    int64_t slab_cap = 0;     // bytes
+    int64_t slab_elems = 0;
     int32_t* cid = nullptr;
     double* val64 = nullptr;
     void* post = nullptr;
@@ -120,7 +124,9 @@ void free_all(ivf_handle* h) {
     for (int b = 0; b < 2; ++b) {
         dfree(h->mm_ptr[b]); dfree(h->mm_idx[b]); dfree(h->mm_val[b]); dfree(h->mm_row[b]);
     }
-    dfree(h->ivf_ptr); dfree(h->sub_ptr); dfree(h->cid); dfree(h->val64);
+    dfree(h->ivf_ptr); dfree(h->desc); dfree(h->dsz); dfree(h->cid); dfree(h->val64);
+    if (h->slab) (void)hipFree(h->slab);
+    h->slab = nullptr;
     if (h->post) (void)hipFree(h->post);
     h->post = nullptr;
     dfree(h->rec); dfree(h->prev); dfree(h->seed_assign); dfree(h->rho); dfree(h->best);
@@ -142,8 +148,9 @@ ivf_status ensure_sort(ivf_handle* h, int64_t need) {
     HIPCHK(h, dalloc(&h->keys_alt, cap));
     HIPCHK(h, dalloc(&h->vals_alt, cap));
     HIPCHK(h, dalloc(&h->iota, cap));
-    h->tmp_bytes = std::max(radix_tmp_bytes(cap),
-                            scan_tmp_bytes(std::max<int64_t>(cap, (int64_t)h->k + 1)));
+    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(cap, (int64_t)h->k + 1),
+                                             h->d * (int64_t)h->plan.R + 1);
+    h->tmp_bytes = std::max(radix_tmp_bytes(cap), scan_tmp_bytes(scan_n));
     HIPCHK(h, hipMalloc(&h->tmp, h->tmp_bytes));
     HIPCHK(h, launch_iota(h->iota, cap, h->stream));
     h->sort_cap = cap;
@@ -200,6 +207,7 @@ ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM) {
     a.k_r = h->plan.k_r;
     a.R = h->plan.R;
     a.valtype = h->opt.valtype;
+    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold : 0.5f;
     a.mm_idx = h->mm_idx[b];
     a.mm_val = h->mm_val[b];
     a.mm_row = h->mm_row[b];
@@ -209,12 +217,30 @@ ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM) {
     a.vals_alt = h->vals_alt;
     a.iota = h->iota;
     a.ivf_ptr = h->ivf_ptr;
-    a.sub_ptr = h->sub_ptr;
+    a.desc = h->desc;
+    a.dsz = h->dsz;
     a.cid = h->cid;
     a.val64 = h->val64;
     a.post = h->post;
     a.tmp = h->tmp;
     HIPCHK(h, launch_build_ivf(a, h->stream));
+    // size the dense slabs (the scanned total) before filling them
+    int64_t elems = 0;
+    HIPCHK(h, hipMemcpyAsync(&elems, h->dsz + h->d * h->plan.R, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    const int64_t bytes = elems * (h->opt.valtype == IVF_VAL_F32 ? 4 : 2);
+    if (bytes > h->slab_cap) {
+        if (h->slab) (void)hipFree(h->slab);
+        h->slab = nullptr;
+        h->slab_cap = 0;
+        const int64_t cap = std::max<int64_t>(bytes, bytes + bytes / 4);
+        HIPCHK(h, hipMalloc(&h->slab, (size_t)cap));
+        h->slab_cap = cap;
+    }
+    a.slab = h->slab;
+    HIPCHK(h, launch_build_slabs(a, elems, h->stream));
+    h->slab_elems = elems;
     return IVF_OK;
 }
 
@@ -284,13 +310,15 @@ ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err)
         if (err) *err = "k must be >= 1";
         return IVF_ERR_ARG;
     }
-    int32_t kr_max = (o && o->cluster_range > 0) ? o->cluster_range : 4096;
+    // 1280 clusters per tile and 8 tiles per workgroup (40 KB of LDS, 4
+    // workgroups and 32 waves per CU) measured best at 8M documents x k = 10,000
+    int32_t kr_max = (o && o->cluster_range > 0) ? o->cluster_range : 1280;
     if (kr_max > 32768) {
         if (err) *err = "cluster_range above 32768 (LDS tile and 16-bit local ids)";
         return IVF_ERR_ARG;
     }
     const bool forced_waves = o && o->waves_per_wg > 0;
-    int32_t waves = forced_waves ? o->waves_per_wg : 4;
+    int32_t waves = forced_waves ? o->waves_per_wg : 8;
     if (waves > kMaxWaves) {
         if (err) *err = "waves_per_wg above 16";
         return IVF_ERR_ARG;
@@ -481,7 +509,8 @@ ivf_status ivf_build(const ivf_csr* X, int32_t k, const ivf_options* opts, ivf_h
     BST(ensure_mm(h, 0, 1));
     BST(ensure_mm(h, 1, 1));
     BCHK(dalloc(&h->ivf_ptr, d + 1));
-    BCHK(dalloc(&h->sub_ptr, d * ((int64_t)plan.R + 1)));
+    BCHK(dalloc(&h->desc, d * (int64_t)plan.R));
+    BCHK(dalloc(&h->dsz, d * (int64_t)plan.R + 1));
     BST(ensure_ivf(h, 1));
     // assignment scratch
     BCHK(dalloc(&h->rec, n * (int64_t)plan.R));
@@ -574,7 +603,7 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
                              hipMemcpyDeviceToDevice, s));
     WalkArgs w{};
     w.x_ptr = h->x_ptr; w.x_idx = h->x_idx; w.x_val = h->x_val; w.n = h->n;
-    w.sub_ptr = h->sub_ptr; w.post = h->post;
+    w.desc = h->desc; w.post = h->post; w.slab = h->slab;
     w.k = h->k; w.k_r = p.k_r; w.R = p.R; w.chunk = p.chunk; w.tile_stride = p.tile_stride;
     w.items_per_range = (h->n + p.chunk - 1) / p.chunk;
     w.cnt = h->cnt; w.rec = h->rec;

@@ -100,6 +100,61 @@ __device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, i
     }
 }
 
+// A dense slab (the range's clusters in order, zeros for absent ones) added
+// into the tile: 4 consecutive slots per lane, 128-bit LDS reads and writes.
+// Adding an exact zero leaves a slot unchanged, so the tile equals the one
+// the sparse slice would give.
+template <int VT> struct Slab;
+template <> struct Slab<IVF_VAL_F32> {
+    using T = float4;
+    __device__ static float4 widen(T x) { return x; }
+};
+template <int VT> struct Slab16 {
+    using T = ushort4;
+    __device__ static float4 widen(T x) {
+        return make_float4(widen16(x.x, VT), widen16(x.y, VT), widen16(x.z, VT), widen16(x.w, VT));
+    }
+};
+template <> struct Slab<IVF_VAL_BF16> : Slab16<IVF_VAL_BF16> {};
+template <> struct Slab<IVF_VAL_F16> : Slab16<IVF_VAL_F16> {};
+
+constexpr int kDenseUnroll = 4;
+
+template <int VT>
+__device__ inline void walk_dense(const typename Slab<VT>::T* __restrict__ S, int32_t kr4, float v,
+                                  float* tile, int lane) {
+    using D = Slab<VT>;
+    float4* t4 = reinterpret_cast<float4*>(tile);
+    int32_t g0 = 0;   // groups of 4 slots; kr4 groups in the slab
+    for (; g0 + kDenseUnroll * kWave <= kr4; g0 += kDenseUnroll * kWave) {
+        typename D::T x[kDenseUnroll];
+#pragma unroll
+        for (int u = 0; u < kDenseUnroll; ++u) x[u] = S[g0 + u * kWave + lane];
+        float4 r[kDenseUnroll];
+#pragma unroll
+        for (int u = 0; u < kDenseUnroll; ++u) r[u] = t4[g0 + u * kWave + lane];
+#pragma unroll
+        for (int u = 0; u < kDenseUnroll; ++u) {
+            const float4 m = D::widen(x[u]);
+            float4 o;
+            o.x = r[u].x + v * m.x;
+            o.y = r[u].y + v * m.y;
+            o.z = r[u].z + v * m.z;
+            o.w = r[u].w + v * m.w;
+            t4[g0 + u * kWave + lane] = o;
+        }
+    }
+    for (int32_t g = g0 + lane; g < kr4; g += kWave) {
+        const float4 m = D::widen(S[g]);
+        float4 o = t4[g];
+        o.x = o.x + v * m.x;
+        o.y = o.y + v * m.y;
+        o.z = o.z + v * m.z;
+        o.w = o.w + v * m.w;
+        t4[g] = o;
+    }
+}
+
 // Wave-wide merge of (best, id, second): larger best wins, lower id on equal
 // best; second collects the largest score of every other cluster.
 __device__ inline void top2_combine(float& b, int32_t& id, float& s, float ob, int32_t oid,
@@ -143,20 +198,26 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_walk(WalkArgs a) {
             for (int64_t h0 = hb; h0 < he; h0 += kWave) {
                 const int cnt = (int)min((int64_t)kWave, he - h0);
                 float v = 0.f;
-                int64_t pb = 0, pe = 0;
+                int64_t pos = 0, count = 0;
                 if (lane < cnt) {
                     const int32_t t = a.x_idx[h0 + lane];
                     v = a.x_val[h0 + lane];
-                    const int64_t* sp = a.sub_ptr + (int64_t)t * (a.R + 1) + r;
-                    pb = sp[0];
-                    pe = sp[1];
+                    const SliceDesc ds = a.desc[(int64_t)t * a.R + r];
+                    pos = ds.pos;
+                    count = ds.count;
                 }
                 for (int hh = 0; hh < cnt; ++hh) {
-                    const int64_t qb = rl64(pb, hh), qe = rl64(pe, hh);
+                    const int64_t p = rl64(pos, hh), c = rl64(count, hh);
                     const float vv = rlf(v, hh);
-                    m += (int32_t)(qe - qb);
-                    walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), qb,
-                                   qe, vv, tile, base, lane);
+                    m += (int32_t)c;
+                    if (p >= 0)
+                        walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p,
+                                       p + c, vv, tile, base, lane);
+                    else
+                        walk_dense<VT>(reinterpret_cast<const typename Slab<VT>::T*>(
+                                           reinterpret_cast<const char*>(a.slab) +
+                                           (-p - 1) * (VT == IVF_VAL_F32 ? 4 : 2)),
+                                       (kr + 3) >> 2, vv, tile, lane);
                 }
             }
             // fused top-2 over the tile, clearing it for the next object

@@ -14,17 +14,26 @@ constexpr int kWave = 64;
 constexpr int kLdsBytes = 160 * 1024;      // LDS per CU (and per workgroup) on gfx950
 constexpr int kMaxWaves = 16;
 
-// Launch plan of the assignment walk (see plan.cpp).
+// Launch plan of the assignment walk (chosen by make_plan).
 struct Plan {
     int32_t k = 0;
     int32_t k_r = 0;          // clusters per FP32 score tile (one range)
     int32_t R = 0;            // number of cluster ranges
     int32_t waves = 0;        // waves per workgroup, each owning one tile
     int32_t chunk = 0;        // objects per work-queue item
-    int32_t tile_stride = 0;  // floats per tile (k_r rounded up to 256)
+    int32_t tile_stride = 0;  // floats per tile (k_r rounded up to a multiple of 4)
     int32_t k_r64 = 0;        // clusters per FP64 re-score tile
     int32_t R64 = 0;
     int32_t lds_bytes = 0;    // per workgroup of the walk
+};
+
+// One (term, cluster range) slice of the inverted file.  pos >= 0: sparse,
+// entries [pos, pos + count) of the posting array; pos < 0: dense slab of the
+// range's width at element offset -pos - 1 of the slab array.  count is the
+// number of clusters of the range holding the term either way.
+struct SliceDesc {
+    int64_t pos;
+    int64_t count;
 };
 
 // Per (object, range) result of the walk.

@@ -10,8 +10,9 @@ struct WalkArgs {
     const int32_t* x_idx;
     const float* x_val;
     int64_t n;
-    const int64_t* sub_ptr;   // [d * (R + 1)]: per term, first entry of every range
+    const SliceDesc* desc;    // [d * R]: per (term, range) slice, sparse or dense
     const void* post;         // uint2 {cluster, f32} or uint32 {local cluster | 16-bit value}
+    const void* slab;         // dense slices: float or 16-bit values, zeros for absent clusters
     int32_t k, k_r, R, chunk, tile_stride;
     int64_t items_per_range;  // ceil(n / chunk)
     Counters* cnt;
@@ -143,6 +144,7 @@ hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStre
 struct IvfArgs {
     int64_t d, nnzM;
     int32_t k, k_r, R, valtype;
+    float dense_threshold;
     const int32_t* mm_idx;
     const double* mm_val;
     const int32_t* mm_row;
@@ -152,16 +154,22 @@ struct IvfArgs {
     uint32_t* vals_alt;
     const uint32_t* iota;
     int64_t* ivf_ptr;    // [d + 1]
-    int64_t* sub_ptr;    // [d * (R + 1)]
+    SliceDesc* desc;     // [d * R]
+    int64_t* dsz;        // [d * R + 1] dense slab sizes, then their offsets (scanned)
+    void* slab;          // dense slabs (sized by the first phase)
     int32_t* cid;        // [nnzM]
     double* val64;       // [nnzM]
     void* post;          // [nnzM] uint2 or uint32
     void* tmp;
 };
 
-// Inverted-file rebuild: stable sort of the mean entries by term, then lists
-// in ascending cluster order with the stored-precision values.
+// Inverted-file rebuild, phase 1: stable sort of the mean entries by term,
+// lists in ascending cluster order with the stored-precision values, slice
+// descriptors and the scanned dense-slab offsets (total at dsz[d * R]).
 hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s);
+// Phase 2 (after the slab array is sized): dense slabs filled, descriptors
+// of dense slices pointed at them.
+hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_elems, hipStream_t s);
 hipError_t launch_seed_assign(const int32_t* seeds, int32_t k, int64_t n, int32_t* assign,
                               hipStream_t s);
 

@@ -393,17 +393,66 @@ __global__ void k_ivf_ptr(const uint32_t* skeys, int64_t nnzM, int64_t d, int64_
     ptr[t] = lo;
 }
 
-__global__ void k_sub_ptr(const int64_t* ptr, const int32_t* cid, int64_t d, int32_t R,
-                          int32_t k_r, int64_t* sub) {
+// Per (term, range) slice: sparse start and count; dense slab size when the
+// slice holds at least `theta` of the range's clusters.
+__global__ void k_desc(const int64_t* ptr, const int32_t* cid, int64_t d, int32_t k, int32_t R,
+                       int32_t k_r, float theta, SliceDesc* desc, int64_t* dsz) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= d) return;
+    if (t >= d) {
+        if (t == d) dsz[d * R] = 0;
+        return;
+    }
     const int64_t a = ptr[t], b = ptr[t + 1];
     int64_t lo = a;
     for (int32_t r = 0; r < R; ++r) {
-        lo = lower_bound_i32(cid, lo, b, r * k_r);
-        sub[t * (R + 1) + r] = lo;
+        const int64_t hi = lower_bound_i32(cid, lo, b, (r + 1) * k_r);
+        const int64_t cnt = hi - lo;
+        const int32_t kr = min(k_r, k - r * k_r);
+        SliceDesc ds;
+        ds.pos = lo;
+        ds.count = cnt;
+        desc[t * R + r] = ds;
+        dsz[t * R + r] = (cnt > 0 && (float)cnt >= theta * (float)kr) ? (int64_t)((kr + 3) & ~3) : 0;
+        lo = hi;
     }
-    sub[t * (R + 1) + R] = b;
+}
+
+__global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, const int64_t* dsz_next,
+                             int64_t nslices) {
+    // a slice is dense iff its scanned offset grows: doff[s + 1] > doff[s]
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslices;
+         s += (int64_t)gridDim.x * blockDim.x)
+        if (doff[s + 1] > doff[s]) desc[s].pos = -(doff[s] + 1);
+    (void)dsz_next;
+}
+
+template <typename T>
+__global__ void k_zero_t(T* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (T)0;
+}
+
+// Dense slabs take every entry of their slice at its cluster's offset.
+__global__ void k_slab_scatter(const uint32_t* __restrict__ skeys, const int32_t* __restrict__ cid,
+                               const void* __restrict__ post, const SliceDesc* __restrict__ desc,
+                               int64_t nnzM, int32_t R, int32_t k_r, int valtype,
+                               void* __restrict__ slab) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = skeys[q];
+        const int32_t j = cid[q];
+        const int32_t r = j / k_r;
+        const int64_t pos = desc[t * R + r].pos;
+        if (pos >= 0) continue;
+        const int64_t at = (-pos - 1) + (j - r * k_r);
+        if (valtype == IVF_VAL_F32)
+            reinterpret_cast<float*>(slab)[at] =
+                __uint_as_float(reinterpret_cast<const uint2*>(post)[q].y);
+        else
+            reinterpret_cast<uint16_t*>(slab)[at] =
+                (uint16_t)(reinterpret_cast<const uint32_t*>(post)[q] >> 16);
+    }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
@@ -540,7 +589,24 @@ hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
         HIP_RET(hipGetLastError());
     }
     k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.d, a.ivf_ptr);
-    k_sub_ptr<<<grid_for(a.d), kThreads, 0, s>>>(a.ivf_ptr, a.cid, a.d, a.R, a.k_r, a.sub_ptr);
+    k_desc<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.ivf_ptr, a.cid, a.d, a.k, a.R, a.k_r,
+                                                  a.dense_threshold, a.desc, a.dsz);
+    HIP_RET(hipGetLastError());
+    return exclusive_scan_i64(a.dsz, a.dsz, a.d * a.R + 1, a.tmp, s);
+}
+
+hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_elems, hipStream_t s) {
+    const int64_t ns = a.d * a.R;
+    if (slab_elems <= 0) return hipSuccess;
+    k_desc_dense<<<capped(ns), kThreads, 0, s>>>(a.desc, a.dsz, nullptr, ns);
+    if (a.valtype == IVF_VAL_F32)
+        k_zero_t<float><<<capped(slab_elems), kThreads, 0, s>>>(
+            reinterpret_cast<float*>(a.slab), slab_elems);
+    else
+        k_zero_t<uint16_t><<<capped(slab_elems), kThreads, 0, s>>>(
+            reinterpret_cast<uint16_t*>(a.slab), slab_elems);
+    k_slab_scatter<<<capped(a.nnzM), kThreads, 0, s>>>(a.keys, a.cid, a.post, a.desc, a.nnzM, a.R,
+                                                       a.k_r, a.valtype, a.slab);
     return hipGetLastError();
 }
 

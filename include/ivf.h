@@ -182,13 +182,14 @@ ivf_status ivf_get_means(ivf_handle* h, ivf_means* out);
 
 /*
  * ivf_get_scores: per-object results of the last ivf_assign (device outputs,
- * any may be NULL): best[n] FP32 top-1 score of the tile walk, second[n] FP32
- * best score of any other cluster, rho[n] the score used for the objective
- * (FP64; the FP64 re-score where one was made), flags[n] (bit 0: certified,
- * bit 1: re-scored in FP64, bit 2: no shared term).  Synchronises.
+ * any may be NULL): best[n] FP32 top-1 score of the tile walk, best_id[n] its
+ * cluster (-1 if no term is shared), second[n] FP32 best score of any other
+ * cluster, rho[n] the score used for the objective (FP64; the FP64 re-score
+ * where one was made), flags[n] (bit 0: certified, bit 1: re-scored in FP64,
+ * bit 2: no shared term).  Synchronises.
  */
-ivf_status ivf_get_scores(ivf_handle* h, float* best, float* second, double* rho,
-                          uint8_t* flags);
+ivf_status ivf_get_scores(ivf_handle* h, float* best, int32_t* best_id, float* second,
+                          double* rho, uint8_t* flags);
 
 /*
  * ivf_get_plan: the launch plan chosen by ivf_build: plan[0] clusters per

@@ -128,15 +128,17 @@ class IVFKMeans:
         return ptr, idx[:nnz], val[:nnz]
 
     def get_scores(self):
+        """(best FP32, best cluster, second FP32, rho FP64, flags) per object."""
         import torch
         dev = self._keep[0].device
         best = torch.empty(self.n, dtype=torch.float32, device=dev)
+        best_id = torch.empty(self.n, dtype=torch.int32, device=dev)
         second = torch.empty(self.n, dtype=torch.float32, device=dev)
         rho = torch.empty(self.n, dtype=torch.float64, device=dev)
         flags = torch.empty(self.n, dtype=torch.uint8, device=dev)
-        check(_lib.get().ivf_get_scores(self._h, _ptr(best), _ptr(second), _ptr(rho),
-                                      _ptr(flags)), self._h)
-        return best, second, rho, flags
+        check(_lib.get().ivf_get_scores(self._h, _ptr(best), _ptr(best_id), _ptr(second),
+                                        _ptr(rho), _ptr(flags)), self._h)
+        return best, best_id, second, rho, flags
 
     @property
     def plan(self):

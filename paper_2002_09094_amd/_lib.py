@@ -61,7 +61,7 @@ SIGNATURES = {
     "ivf_update": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_iterate": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_get_means": (c_int32, [c_void_p, ctypes.POINTER(ivf_means)]),
-    "ivf_get_scores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ivf_get_scores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ivf_get_plan": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "ivf_plan_shape": (c_int32, [c_int32, ctypes.POINTER(ivf_options), ctypes.POINTER(c_int32)]),
     "ivf_cert_bound": (c_int32, [c_int32, c_int64, ctypes.POINTER(c_double)]),

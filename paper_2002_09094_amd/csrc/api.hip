@@ -703,11 +703,13 @@ ivf_status ivf_get_means(ivf_handle* h, ivf_means* out) {
     return IVF_OK;
 }
 
-ivf_status ivf_get_scores(ivf_handle* h, float* best, float* second, double* rho,
-                          uint8_t* flags) {
+ivf_status ivf_get_scores(ivf_handle* h, float* best, int32_t* best_id, float* second,
+                          double* rho, uint8_t* flags) {
     if (!h) return IVF_ERR_ARG;
     const size_t n = (size_t)h->n;
     if (best) HIPCHK(h, hipMemcpyAsync(best, h->best, n * 4, hipMemcpyDeviceToDevice, h->stream));
+    if (best_id)
+        HIPCHK(h, hipMemcpyAsync(best_id, h->best_id, n * 4, hipMemcpyDeviceToDevice, h->stream));
     if (second)
         HIPCHK(h, hipMemcpyAsync(second, h->second, n * 4, hipMemcpyDeviceToDevice, h->stream));
     if (rho) HIPCHK(h, hipMemcpyAsync(rho, h->rho, n * 8, hipMemcpyDeviceToDevice, h->stream));

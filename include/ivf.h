@@ -225,6 +225,86 @@ const char* ivf_last_error(const ivf_handle* h);
 /* Static name of a status code. */
 const char* ivf_status_str(int32_t status);
 
+/* ------------------------------------------------------------------ batches
+ * Many independent clustering instances (different object sets, k, or seeds
+ * of one set: restarts) advanced together.  Every iteration walks ALL
+ * instances in one persistent launch of the assignment kernel (work items of
+ * every instance in one queue, one LDS tile width for all), then runs each
+ * instance's merge, FP64 re-score and update.  Each instance computes exactly
+ * what a single handle of the same options computes (Alg. 3 per instance):
+ * assignments and means are bit-identical to one ivf_handle per instance.
+ *
+ * Execution: the first two iterations run eagerly and size every buffer;
+ * then capacities are fixed (1.5x what was needed) and one iteration of the
+ * whole batch is recorded as a HIP graph (two graphs: the means' double
+ * buffer alternates) and replayed.  A replay whose new means would exceed a
+ * fixed capacity is detected from device flags after the replay, that
+ * instance's update is redone eagerly with larger buffers and the graphs are
+ * recorded again, so results never depend on the capacities.
+ * Tiles: with opts->cluster_range == 0 an autotuner times the batched walk
+ * over a few (clusters per tile, waves per workgroup) shapes on the means of
+ * the second iteration and keeps the fastest; otherwise the given shape is used.
+ */
+typedef struct ivf_batch ivf_batch;
+
+/*
+ * ivf_batch_build: count instances; X[i] (host array of count ivf_csr, device
+ * pointers inside, borrowed until ivf_batch_destroy) and k[i] (host int32).
+ * Instances whose X[i] names the same device arrays share one term-major view.
+ * opts applies to every instance (NULL: defaults); opts->stream NULL makes the
+ * batch create a stream of its own (graph capture cannot use the null stream).
+ * Errors as ivf_build; text from ivf_batch_last_error(NULL).
+ */
+ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
+                           const ivf_options* opts, ivf_batch** out);
+
+/* Seeds of every instance: seeds[i] is a device int32 [k[i]] array (host
+ * array of count pointers).  As ivf_init_seeds per instance.  Synchronises. */
+ivf_status ivf_batch_init_seeds(ivf_batch* b, const int32_t* const* seeds);
+
+/* Caller-given means of instance `inst` (as ivf_set_means).  Only before the
+ * first ivf_batch_iterate; all instances need means before iterating. */
+ivf_status ivf_batch_set_means(ivf_batch* b, int32_t inst, const ivf_means* M);
+
+/*
+ * ivf_batch_iterate: `iters` Lloyd iterations of every instance.  assign is a
+ * host array of count device pointers, assign[i] int32 [n_i] (previous
+ * assignment in, new one out, -1 = unassigned); the same pointers should be
+ * passed on every call (new pointers force the graphs to be recorded again).
+ * stats (host, [iters * count], iteration-major) may be NULL; when given, each
+ * entry holds that instance's assignment and update fields, and assign_ms the
+ * device time of the whole batch iteration.  Synchronises before returning.
+ */
+ivf_status ivf_batch_iterate(ivf_batch* b, int32_t iters, int32_t* const* assign,
+                             ivf_stats* stats);
+
+/* Means of instance `inst`, two-call form as ivf_get_means.  Synchronises. */
+ivf_status ivf_batch_get_means(ivf_batch* b, int32_t inst, ivf_means* out);
+
+/*
+ * ivf_batch_set_slack: the fixed capacities become need * (1 + frac) + abs
+ * entries (defaults 0.5 and 1024), need being what the eager iterations used.
+ * Less slack saves memory across many instances at the price of more graph
+ * re-recordings after overflows; results do not depend on it.  0 <= frac <= 64,
+ * abs >= 0, else IVF_ERR_ARG.
+ */
+ivf_status ivf_batch_set_slack(ivf_batch* b, double frac, int64_t abs_entries);
+
+/*
+ * ivf_batch_get_plan: plan[0] clusters-per-tile limit, plan[1] waves per
+ * workgroup, plan[2] floats per tile (the widest range of any instance),
+ * plan[3] workgroups of the persistent walk, plan[4] 1 once the iteration is
+ * recorded as graphs, plan[5] 1 once the autotuner has run, plan[6] times the
+ * iteration was recorded, plan[7] replays redone after a capacity overflow.
+ */
+ivf_status ivf_batch_get_plan(const ivf_batch* b, int32_t plan[8]);
+
+/* Frees the batch, its instances and its stream if it created one. */
+void ivf_batch_destroy(ivf_batch* b);
+
+/* Text of the last error on b (or of the last ivf_batch_build failure if b is NULL). */
+const char* ivf_batch_last_error(const ivf_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

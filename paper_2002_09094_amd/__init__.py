@@ -20,7 +20,7 @@ def library():
 
 VALTYPES = {"f32": IVF_VAL_F32, "bf16": IVF_VAL_BF16, "f16": IVF_VAL_F16}
 
-__all__ = ["IVFKMeans", "IvfError", "VALTYPES", "plan_shape", "cert_bound"]
+__all__ = ["IVFKMeans", "IVFBatch", "IvfError", "VALTYPES", "plan_shape", "cert_bound"]
 
 
 def _ptr(t):
@@ -175,6 +175,126 @@ class IVFKMeans:
         if getattr(self, "_h", None):
             _lib.get().ivf_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class IVFBatch:
+    """Many clustering instances advanced together (one persistent walk launch
+    per iteration for all of them, the iteration replayed as HIP graphs).
+
+    sets: list of (indptr, indices, values, d) CUDA tensor tuples, one per
+    instance (instances may share one tuple: restarts of one object set);
+    ks: clusters of each instance.  Options as IVFKMeans, applied to all.
+    """
+
+    def __init__(self, sets, ks, *, valtype="f32", certify=True, cluster_range=0,
+                 waves_per_wg=0, dense_threshold=0.0):
+        import torch
+        if len(sets) != len(ks) or not sets:
+            raise ValueError("need one k per object set")
+        self.count = len(sets)
+        xs = (_lib.ivf_csr * self.count)()
+        self._keep = []
+        self.n, self.k, self.d = [], [int(k) for k in ks], []
+        for i, (indptr, indices, values, d) in enumerate(sets):
+            _need_cuda(indptr, torch.int64, "indptr")
+            _need_cuda(indices, torch.int32, "indices")
+            _need_cuda(values, torch.float32, "values")
+            self._keep.append((indptr, indices, values))
+            self.n.append(indptr.numel() - 1)
+            self.d.append(int(d))
+            xs[i] = _lib.ivf_csr(indptr.numel() - 1, int(d), indices.numel(), _ptr(indptr),
+                                 _ptr(indices), _ptr(values))
+        karr = (ctypes.c_int32 * self.count)(*self.k)
+        # the batch creates and owns its stream (graphs cannot record the null stream)
+        o = _options(valtype, certify, cluster_range, waves_per_wg, 0, False, dense_threshold,
+                     None)
+        b = ctypes.c_void_p()
+        _lib.check_batch(_lib.get().ivf_batch_build(self.count, xs, karr, ctypes.byref(o),
+                                                    ctypes.byref(b)))
+        self._b = b
+        self._device = sets[0][0].device
+
+    def _ptrs(self, tensors, dtype, sizes, name):
+        import torch
+        if len(tensors) != self.count:
+            raise ValueError("need one %s per instance" % name)
+        arr = (ctypes.c_void_p * self.count)()
+        for i, t in enumerate(tensors):
+            _need_cuda(t, dtype, name)
+            if t.numel() != sizes[i]:
+                raise ValueError("%s[%d] has %d entries, expected %d" % (name, i, t.numel(),
+                                                                         sizes[i]))
+            arr[i] = t.data_ptr()
+        return arr
+
+    def init_seeds(self, seeds):
+        import torch
+        torch.cuda.synchronize()
+        arr = self._ptrs(seeds, torch.int32, self.k, "seeds")
+        _lib.check_batch(_lib.get().ivf_batch_init_seeds(self._b, arr), self._b)
+
+    def set_means(self, inst, indptr, indices, values):
+        import torch
+        _need_cuda(indptr, torch.int64, "indptr")
+        _need_cuda(indices, torch.int32, "indices")
+        _need_cuda(values, torch.float64, "values")
+        torch.cuda.synchronize()
+        m = _lib.ivf_means(self.k[inst], self.d[inst], indices.numel(), _ptr(indptr),
+                           _ptr(indices), _ptr(values))
+        _lib.check_batch(_lib.get().ivf_batch_set_means(self._b, int(inst), ctypes.byref(m)),
+                         self._b)
+
+    def iterate(self, iters, assigns, stats=True):
+        """Run iters iterations; assigns: one int32 [n_i] CUDA tensor per instance.
+        Returns per-iteration lists of per-instance stats dicts (or None)."""
+        import torch
+        arr = self._ptrs(assigns, torch.int32, self.n, "assign")
+        torch.cuda.synchronize()   # the batch's stream does not wait for torch's
+        iters = int(iters)
+        st = (_lib.ivf_stats * max(iters * self.count, 1))() if stats else None
+        _lib.check_batch(_lib.get().ivf_batch_iterate(self._b, iters, arr, st), self._b)
+        if not stats:
+            return None
+        return [[st[r * self.count + i].to_dict() for i in range(self.count)]
+                for r in range(iters)]
+
+    def get_means(self, inst):
+        import torch
+        m = _lib.ivf_means()
+        _lib.check_batch(_lib.get().ivf_batch_get_means(self._b, int(inst), ctypes.byref(m)),
+                         self._b)
+        nnz = m.nnz
+        ptr = torch.empty(self.k[inst] + 1, dtype=torch.int64, device=self._device)
+        idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=self._device)
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device=self._device)
+        m2 = _lib.ivf_means(self.k[inst], self.d[inst], nnz, _ptr(ptr), _ptr(idx), _ptr(val))
+        _lib.check_batch(_lib.get().ivf_batch_get_means(self._b, int(inst), ctypes.byref(m2)),
+                         self._b)
+        return ptr, idx[:nnz], val[:nnz]
+
+    def set_slack(self, frac, abs_entries):
+        """Fixed capacities = need * (1 + frac) + abs_entries (defaults 0.5, 1024)."""
+        _lib.check_batch(_lib.get().ivf_batch_set_slack(self._b, float(frac),
+                                                        int(abs_entries)), self._b)
+
+    @property
+    def plan(self):
+        plan = (ctypes.c_int32 * 8)()
+        _lib.check_batch(_lib.get().ivf_batch_get_plan(self._b, plan), self._b)
+        keys = ("kr_max", "waves", "tile_stride", "grid", "graphs", "tuned", "captures",
+                "recoveries")
+        return dict(zip(keys, list(plan)))
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.get().ivf_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

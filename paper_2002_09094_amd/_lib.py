@@ -68,6 +68,18 @@ SIGNATURES = {
     "ivf_destroy": (None, [c_void_p]),
     "ivf_last_error": (ctypes.c_char_p, [c_void_p]),
     "ivf_status_str": (ctypes.c_char_p, [c_int32]),
+    # batches
+    "ivf_batch_build": (c_int32, [c_int32, ctypes.POINTER(ivf_csr), ctypes.POINTER(c_int32),
+                                  ctypes.POINTER(ivf_options), ctypes.POINTER(c_void_p)]),
+    "ivf_batch_init_seeds": (c_int32, [c_void_p, ctypes.POINTER(c_void_p)]),
+    "ivf_batch_set_means": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ivf_means)]),
+    "ivf_batch_iterate": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_void_p),
+                                    ctypes.POINTER(ivf_stats)]),
+    "ivf_batch_get_means": (c_int32, [c_void_p, c_int32, ctypes.POINTER(ivf_means)]),
+    "ivf_batch_set_slack": (c_int32, [c_void_p, c_double, c_int64]),
+    "ivf_batch_get_plan": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
+    "ivf_batch_destroy": (None, [c_void_p]),
+    "ivf_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }
 
 
@@ -103,5 +115,12 @@ class IvfError(RuntimeError):
 def check(status, handle=None):
     if status != IVF_OK:
         msg = get().ivf_last_error(handle)
+        raise IvfError(status, msg.decode() if msg else "")
+    return status
+
+
+def check_batch(status, batch=None):
+    if status != IVF_OK:
+        msg = get().ivf_batch_last_error(batch)
         raise IvfError(status, msg.decode() if msg else "")
     return status

@@ -1,5 +1,6 @@
-// C ABI of the library (declared in include/ivf.h): handle, validation,
-// planning, memory and the order of launches for one Lloyd iteration.
+// C ABI of the library (declared in include/ivf.h): handles, validation,
+// planning, memory, the order of launches for one Lloyd iteration, and the
+// batch of many instances replayed as captured HIP graphs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,33 +9,37 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "ivf_internal.h"
 #include "kernels.h"
 
 using namespace ivf;
 
-struct ivf_handle {
-    // configuration
-    int64_t n = 0, d = 0, nnz = 0;
-    int32_t k = 0;
-    ivf_options opt{};
-    hipStream_t stream = nullptr;
-    Plan plan;
-    int device = 0, cus = 0;
-    int walk_grid = 0, rescore_grid = 0;
-    // objects (borrowed)
-    const int64_t* x_ptr = nullptr;
-    const int32_t* x_idx = nullptr;
-    const float* x_val = nullptr;
-    // term-major view of the objects
-    int32_t* xt_obj = nullptr;
-    int32_t* xt_term = nullptr;
-    float* xt_val = nullptr;
-    int16_t* shift = nullptr;
-    int64_t inexact_terms = 0;
-    // sort / segment scratch
-    int64_t sort_cap = 0;
+namespace {
+
+constexpr int kObjBlocks = 1024;
+thread_local std::string g_build_error;
+
+template <typename T>
+hipError_t dalloc(T** p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), (size_t)count * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(reinterpret_cast<void*>(p));
+    p = nullptr;
+}
+
+// Transient buffers of the update and of the inverted-file rebuild.  A batch
+// shares one set, sized for its largest instance.
+struct Scratch {
+    int64_t sort_cap = 0;   // entries of the sort buffers
+    int64_t seg_cap = 0;    // entries of the segment buffers
+    int64_t scan_need = 0;  // largest scan any user runs
     uint32_t *keys = nullptr, *vals = nullptr, *keys_alt = nullptr, *vals_alt = nullptr;
     uint32_t* iota = nullptr;
     uint32_t *flag = nullptr, *segpos = nullptr;
@@ -42,12 +47,93 @@ struct ivf_handle {
     int32_t *seg_j = nullptr, *seg_t = nullptr;
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
-    // clusters
-    int64_t *size = nullptr, *cstart = nullptr, *newcnt = nullptr, *scal = nullptr;
-    double *nrm = nullptr, *objpart = nullptr;
+
+    void release() {
+        dfree(keys); dfree(vals); dfree(keys_alt); dfree(vals_alt); dfree(iota);
+        dfree(flag); dfree(segpos); dfree(seg_acc); dfree(seg_j); dfree(seg_t);
+        if (tmp) (void)hipFree(tmp);
+        tmp = nullptr;
+        sort_cap = seg_cap = 0;
+        tmp_bytes = 0;
+    }
+
+    hipError_t ensure(int64_t sort_need, int64_t seg_need, int64_t scan, hipStream_t s) {
+        scan_need = std::max(scan_need, scan);
+        if (sort_need > sort_cap) {
+            const int64_t cap = std::max<int64_t>(sort_need, sort_cap + sort_cap / 4);
+            dfree(keys); dfree(vals); dfree(keys_alt); dfree(vals_alt); dfree(iota);
+            sort_cap = 0;
+            hipError_t e;
+            if ((e = dalloc(&keys, cap)) != hipSuccess) return e;
+            if ((e = dalloc(&vals, cap)) != hipSuccess) return e;
+            if ((e = dalloc(&keys_alt, cap)) != hipSuccess) return e;
+            if ((e = dalloc(&vals_alt, cap)) != hipSuccess) return e;
+            if ((e = dalloc(&iota, cap)) != hipSuccess) return e;
+            if ((e = launch_iota(iota, cap, s)) != hipSuccess) return e;
+            sort_cap = cap;
+        }
+        if (seg_need > seg_cap) {
+            dfree(flag); dfree(segpos); dfree(seg_acc); dfree(seg_j); dfree(seg_t);
+            seg_cap = 0;
+            hipError_t e;
+            if ((e = dalloc(&flag, seg_need)) != hipSuccess) return e;
+            if ((e = dalloc(&segpos, seg_need)) != hipSuccess) return e;
+            if ((e = dalloc(&seg_acc, seg_need)) != hipSuccess) return e;
+            if ((e = dalloc(&seg_j, seg_need)) != hipSuccess) return e;
+            if ((e = dalloc(&seg_t, seg_need)) != hipSuccess) return e;
+            seg_cap = seg_need;
+        }
+        const size_t need = std::max(radix_tmp_bytes(std::max<int64_t>(sort_cap, 1)),
+                                     scan_tmp_bytes(std::max<int64_t>(
+                                         std::max(sort_cap, seg_cap), scan_need)));
+        if (need > tmp_bytes) {
+            if (tmp) (void)hipFree(tmp);
+            tmp = nullptr;
+            tmp_bytes = 0;
+            hipError_t e = hipMalloc(&tmp, need);
+            if (e != hipSuccess) return e;
+            tmp_bytes = need;
+        }
+        return hipSuccess;
+    }
+};
+
+// Term-major view of one object set and its per-term fixed-point scales;
+// handles clustering the same set share one.
+struct ObjView {
+    const int64_t* x_ptr = nullptr;
+    const int32_t* x_idx = nullptr;
+    const float* x_val = nullptr;
+    int64_t n = 0, d = 0, nnz = 0;
+    int32_t* xt_obj = nullptr;
+    int32_t* xt_term = nullptr;
+    float* xt_val = nullptr;
+    int16_t* shift = nullptr;
+    int64_t inexact = 0;
+
+    void release() { dfree(xt_obj); dfree(xt_term); dfree(xt_val); dfree(shift); }
+};
+
+}  // namespace
+
+struct ivf_handle {
+    int64_t n = 0, d = 0, nnz = 0;
+    int32_t k = 0;
+    ivf_options opt{};
+    hipStream_t stream = nullptr;
+    Plan plan;
+    int device = 0, cus = 0;
+    int walk_grid = 0, rescore_grid = 0;
+    ObjView* ov = nullptr;
+    bool owns_ov = false;
+    Scratch* sc = nullptr;
+    bool owns_sc = false;
+    // capacities fixed (no host synchronisation, no allocation): graph capture
+    bool fixed = false;
     // means, mean-major FP64, double-buffered
     int cur = 0;
     bool has_means = false;
+    bool nnzM_known = true;    // false while the count lives only on the device
     int64_t nnzM = 0;
     int64_t mm_cap[2] = {0, 0};
     int64_t* mm_ptr[2] = {nullptr, nullptr};
@@ -59,13 +145,16 @@ struct ivf_handle {
     int64_t* ivf_ptr = nullptr;
     SliceDesc* desc = nullptr;
     int64_t* dsz = nullptr;
-    void* slab = nullptr;
-    int64_t slab_cap = 0;     // bytes
-    int64_t slab_elems = 0;
     int32_t* cid = nullptr;
     double* val64 = nullptr;
     void* post = nullptr;
-    // assignment scratch
+    void* slab = nullptr;
+    int64_t slab_cap = 0;      // elements
+    int64_t slab_need = 0;     // most elements any rebuild asked for
+    // clusters
+    int64_t *size = nullptr, *cstart = nullptr, *newcnt = nullptr, *scal = nullptr;
+    double *nrm = nullptr, *objpart = nullptr;
+    // assignment
     RangeRec* rec = nullptr;
     int32_t* prev = nullptr;
     int32_t* seed_assign = nullptr;
@@ -83,9 +172,6 @@ struct ivf_handle {
 
 namespace {
 
-constexpr int kObjBlocks = 1024;
-thread_local std::string g_build_error;
-
 ivf_status fail(ivf_handle* h, ivf_status st, const std::string& msg) {
     if (h) h->err = msg;
     else g_build_error = msg;
@@ -100,35 +186,21 @@ ivf_status fail(ivf_handle* h, ivf_status st, const std::string& msg) {
                         std::string(#call) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
-template <typename T>
-hipError_t dalloc(T** p, int64_t count) {
-    *p = nullptr;
-    if (count <= 0) count = 1;
-    return hipMalloc(reinterpret_cast<void**>(p), (size_t)count * sizeof(T));
-}
-
-template <typename T>
-void dfree(T*& p) {
-    if (p) (void)hipFree(reinterpret_cast<void*>(p));
-    p = nullptr;
-}
-
-void free_all(ivf_handle* h) {
-    dfree(h->xt_obj); dfree(h->xt_term); dfree(h->xt_val); dfree(h->shift);
-    dfree(h->keys); dfree(h->vals); dfree(h->keys_alt); dfree(h->vals_alt); dfree(h->iota);
-    dfree(h->flag); dfree(h->segpos); dfree(h->seg_acc); dfree(h->seg_j); dfree(h->seg_t);
-    if (h->tmp) (void)hipFree(h->tmp);
-    h->tmp = nullptr;
-    dfree(h->size); dfree(h->cstart); dfree(h->newcnt); dfree(h->scal);
-    dfree(h->nrm); dfree(h->objpart);
+void free_handle(ivf_handle* h) {
+    if (h->owns_ov && h->ov) { h->ov->release(); delete h->ov; }
+    h->ov = nullptr;
+    if (h->owns_sc && h->sc) { h->sc->release(); delete h->sc; }
+    h->sc = nullptr;
     for (int b = 0; b < 2; ++b) {
         dfree(h->mm_ptr[b]); dfree(h->mm_idx[b]); dfree(h->mm_val[b]); dfree(h->mm_row[b]);
     }
     dfree(h->ivf_ptr); dfree(h->desc); dfree(h->dsz); dfree(h->cid); dfree(h->val64);
-    if (h->slab) (void)hipFree(h->slab);
-    h->slab = nullptr;
     if (h->post) (void)hipFree(h->post);
     h->post = nullptr;
+    if (h->slab) (void)hipFree(h->slab);
+    h->slab = nullptr;
+    dfree(h->size); dfree(h->cstart); dfree(h->newcnt); dfree(h->scal);
+    dfree(h->nrm); dfree(h->objpart);
     dfree(h->rec); dfree(h->prev); dfree(h->seed_assign); dfree(h->rho); dfree(h->best);
     dfree(h->second); dfree(h->best_id); dfree(h->flags); dfree(h->rescore_list);
     dfree(h->part); dfree(h->dscal); dfree(h->cnt);
@@ -136,50 +208,79 @@ void free_all(ivf_handle* h) {
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
 }
 
-// Sort buffers and scan/sort scratch sized for `need` elements.
-ivf_status ensure_sort(ivf_handle* h, int64_t need) {
-    if (need <= h->sort_cap) return IVF_OK;
-    const int64_t cap = std::max<int64_t>(need, h->sort_cap + h->sort_cap / 4);
-    dfree(h->keys); dfree(h->vals); dfree(h->keys_alt); dfree(h->vals_alt); dfree(h->iota);
-    if (h->tmp) (void)hipFree(h->tmp);
-    h->tmp = nullptr;
-    HIPCHK(h, dalloc(&h->keys, cap));
-    HIPCHK(h, dalloc(&h->vals, cap));
-    HIPCHK(h, dalloc(&h->keys_alt, cap));
-    HIPCHK(h, dalloc(&h->vals_alt, cap));
-    HIPCHK(h, dalloc(&h->iota, cap));
-    const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(cap, (int64_t)h->k + 1),
-                                             h->d * (int64_t)h->plan.R + 1);
-    h->tmp_bytes = std::max(radix_tmp_bytes(cap), scan_tmp_bytes(scan_n));
-    HIPCHK(h, hipMalloc(&h->tmp, h->tmp_bytes));
-    HIPCHK(h, launch_iota(h->iota, cap, h->stream));
-    h->sort_cap = cap;
+ivf_status ensure_scratch(ivf_handle* h, int64_t sort_need) {
+    const int64_t scan = std::max<int64_t>((int64_t)h->k + 1, h->d * (int64_t)h->plan.R + 1);
+    if (h->fixed) {
+        if (sort_need <= h->sc->sort_cap && h->nnz <= h->sc->seg_cap && scan <= h->sc->scan_need)
+            return IVF_OK;
+        return fail(h, IVF_ERR_CAPACITY, "scratch exceeds the fixed capacity");
+    }
+    HIPCHK(h, h->sc->ensure(sort_need, h->nnz, scan, h->stream));
     return IVF_OK;
 }
 
-ivf_status ensure_mm(ivf_handle* h, int b, int64_t need) {
+// Mean-major buffer `b` grown to hold `need` entries; the first `keep`
+// entries are carried over (0: the content is about to be overwritten).
+ivf_status ensure_mm(ivf_handle* h, int b, int64_t need, int64_t keep = 0) {
     if (need <= h->mm_cap[b]) return IVF_OK;
+    if (h->fixed) return fail(h, IVF_ERR_CAPACITY, "means exceed the fixed capacity");
     const int64_t cap = std::max<int64_t>(need, h->mm_cap[b] + h->mm_cap[b] / 4);
+    keep = std::min(keep, h->mm_cap[b]);
+    int32_t* idx = nullptr;
+    double* val = nullptr;
+    int32_t* row = nullptr;
+    hipError_t e = dalloc(&idx, cap);
+    if (e == hipSuccess) e = dalloc(&val, cap);
+    if (e == hipSuccess) e = dalloc(&row, cap);
+    if (e == hipSuccess && keep > 0) {
+        e = hipMemcpyAsync(idx, h->mm_idx[b], sizeof(int32_t) * (size_t)keep,
+                           hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(val, h->mm_val[b], sizeof(double) * (size_t)keep,
+                               hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(row, h->mm_row[b], sizeof(int32_t) * (size_t)keep,
+                               hipMemcpyDeviceToDevice, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);   // copies done before the frees
+    if (e != hipSuccess) {
+        dfree(idx); dfree(val); dfree(row);
+        return fail(h, e == hipErrorOutOfMemory ? IVF_ERR_OOM : IVF_ERR_HIP,
+                    std::string("growing the means: ") + hipGetErrorString(e));
+    }
     dfree(h->mm_idx[b]); dfree(h->mm_val[b]); dfree(h->mm_row[b]);
-    HIPCHK(h, dalloc(&h->mm_idx[b], cap));
-    HIPCHK(h, dalloc(&h->mm_val[b], cap));
-    HIPCHK(h, dalloc(&h->mm_row[b], cap));
+    h->mm_idx[b] = idx;
+    h->mm_val[b] = val;
+    h->mm_row[b] = row;
     h->mm_cap[b] = cap;
     return IVF_OK;
 }
 
 ivf_status ensure_ivf(ivf_handle* h, int64_t need) {
     if (need > h->ivf_cap) {
+        if (h->fixed) return fail(h, IVF_ERR_CAPACITY, "inverted file exceeds the fixed capacity");
         const int64_t cap = std::max<int64_t>(need, h->ivf_cap + h->ivf_cap / 4);
         dfree(h->cid); dfree(h->val64);
         if (h->post) (void)hipFree(h->post);
         h->post = nullptr;
+        h->ivf_cap = 0;
         HIPCHK(h, dalloc(&h->cid, cap));
         HIPCHK(h, dalloc(&h->val64, cap));
         HIPCHK(h, hipMalloc(&h->post, (size_t)std::max<int64_t>(cap, 1) * 8));
         h->ivf_cap = cap;
     }
-    return ensure_sort(h, need);
+    return ensure_scratch(h, need);
+}
+
+ivf_status ensure_slab(ivf_handle* h, int64_t elems) {
+    if (elems <= h->slab_cap || h->fixed) return IVF_OK;   // fixed: misfits stay sparse
+    if (h->slab) (void)hipFree(h->slab);
+    h->slab = nullptr;
+    h->slab_cap = 0;
+    const int64_t cap = elems + elems / 4;
+    HIPCHK(h, hipMalloc(&h->slab, (size_t)cap * (h->opt.valtype == IVF_VAL_F32 ? 4 : 2)));
+    h->slab_cap = cap;
+    return IVF_OK;
 }
 
 ivf_status read_errors(ivf_handle* h, const char* what) {
@@ -189,6 +290,7 @@ ivf_status read_errors(ivf_handle* h, const char* what) {
     const unsigned long long f = c.error_flags;
     if (!f) return IVF_OK;
     std::string m = std::string(what) + ": ";
+    if (f & kOverflow) return fail(h, IVF_ERR_CAPACITY, m + "new means exceed the fixed capacity");
     if (f & kBadPtr) return fail(h, IVF_ERR_ARG, m + "row pointers inconsistent with sizes");
     if (f & kBadIndex) return fail(h, IVF_ERR_UNSORTED, m + "term id outside [0, d)");
     if (f & kBadOrder) return fail(h, IVF_ERR_UNSORTED, m + "term ids not strictly ascending");
@@ -196,13 +298,9 @@ ivf_status read_errors(ivf_handle* h, const char* what) {
     return fail(h, IVF_ERR_NEGATIVE, m + "value <= 0");
 }
 
-// Rebuild the inverted file from mean-major buffer `b` holding nnzM entries.
-ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM) {
-    ivf_status st = ensure_ivf(h, nnzM);
-    if (st != IVF_OK) return st;
+IvfArgs ivf_args(ivf_handle* h, int b) {
     IvfArgs a{};
     a.d = h->d;
-    a.nnzM = nnzM;
     a.k = h->k;
     a.k_r = h->plan.k_r;
     a.R = h->plan.R;
@@ -211,78 +309,94 @@ ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM) {
     a.mm_idx = h->mm_idx[b];
     a.mm_val = h->mm_val[b];
     a.mm_row = h->mm_row[b];
-    a.keys = h->keys;
-    a.vals = h->vals;
-    a.keys_alt = h->keys_alt;
-    a.vals_alt = h->vals_alt;
-    a.iota = h->iota;
+    a.keys = h->sc->keys;
+    a.vals = h->sc->vals;
+    a.keys_alt = h->sc->keys_alt;
+    a.vals_alt = h->sc->vals_alt;
+    a.iota = h->sc->iota;
     a.ivf_ptr = h->ivf_ptr;
     a.desc = h->desc;
     a.dsz = h->dsz;
     a.cid = h->cid;
     a.val64 = h->val64;
     a.post = h->post;
-    a.tmp = h->tmp;
-    HIPCHK(h, launch_build_ivf(a, h->stream));
-    // size the dense slabs (the scanned total) before filling them
-    int64_t elems = 0;
-    HIPCHK(h, hipMemcpyAsync(&elems, h->dsz + h->d * h->plan.R, sizeof(int64_t),
-                             hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
-    const int64_t bytes = elems * (h->opt.valtype == IVF_VAL_F32 ? 4 : 2);
-    if (bytes > h->slab_cap) {
-        if (h->slab) (void)hipFree(h->slab);
-        h->slab = nullptr;
-        h->slab_cap = 0;
-        const int64_t cap = std::max<int64_t>(bytes, bytes + bytes / 4);
-        HIPCHK(h, hipMalloc(&h->slab, (size_t)cap));
-        h->slab_cap = cap;
-    }
     a.slab = h->slab;
-    HIPCHK(h, launch_build_slabs(a, elems, h->stream));
-    h->slab_elems = elems;
+    a.tmp = h->sc->tmp;
+    return a;
+}
+
+// Inverted file from mean-major buffer `b`.  With nnz_dev the entry count is
+// read on the device (capacity-bounded, no host synchronisation).
+ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM, const int64_t* nnz_dev) {
+    ivf_status st = ensure_ivf(h, nnzM);
+    if (st != IVF_OK) return st;
+    IvfArgs a = ivf_args(h, b);
+    a.nnzM = nnz_dev ? std::min(h->ivf_cap, h->mm_cap[b]) : nnzM;
+    a.nnz_dev = nnz_dev;
+    HIPCHK(h, launch_build_ivf(a, h->stream));
+    if (!h->fixed) {
+        // size the dense slabs (the scanned total) before filling them
+        int64_t elems = 0;
+        HIPCHK(h, hipMemcpyAsync(&elems, h->dsz + h->d * h->plan.R, sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        h->slab_need = std::max(h->slab_need, elems);
+        st = ensure_slab(h, elems);
+        if (st != IVF_OK) return st;
+        a.slab = h->slab;
+    }
+    HIPCHK(h, launch_build_slabs(a, h->slab_cap, h->stream));
     return IVF_OK;
 }
 
 // Update step from `assign`: new means into buffer 1 - cur, then the swap and
-// the inverted-file rebuild.
-ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats) {
+// the inverted-file rebuild.  In fixed mode nothing synchronises or allocates.
+// clear = false keeps the assignment step's counters (the update only adds to
+// `empty` and `error_flags`, which the caller has cleared).
+ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
+                      bool clear = true) {
     const hipStream_t s = h->stream;
-    if (stats) HIPCHK(h, hipEventRecord(h->ev[2], s));
-    HIPCHK(h, launch_clear_counters(h->cnt, s));
+    const bool timed = stats && !h->fixed;
+    if (timed) HIPCHK(h, hipEventRecord(h->ev[2], s));
+    if (clear) HIPCHK(h, launch_clear_counters(h->cnt, s));
     const int o = h->cur, nb = 1 - h->cur;
     UpdateArgs a{};
     a.n = h->n; a.d = h->d; a.nnz = h->nnz; a.k = h->k;
     a.assign = assign;
-    a.xt_obj = h->xt_obj; a.xt_term = h->xt_term; a.xt_val = h->xt_val; a.shift = h->shift;
-    a.keys = h->keys; a.vals = h->vals; a.keys_alt = h->keys_alt; a.vals_alt = h->vals_alt;
-    a.iota = h->iota;
-    a.flag = h->flag; a.segpos = h->segpos; a.seg_acc = h->seg_acc;
-    a.seg_j = h->seg_j; a.seg_t = h->seg_t;
+    a.xt_obj = h->ov->xt_obj; a.xt_term = h->ov->xt_term; a.xt_val = h->ov->xt_val;
+    a.shift = h->ov->shift;
+    a.keys = h->sc->keys; a.vals = h->sc->vals; a.keys_alt = h->sc->keys_alt;
+    a.vals_alt = h->sc->vals_alt; a.iota = h->sc->iota;
+    a.flag = h->sc->flag; a.segpos = h->sc->segpos; a.seg_acc = h->sc->seg_acc;
+    a.seg_j = h->sc->seg_j; a.seg_t = h->sc->seg_t;
     a.size = h->size; a.cstart = h->cstart; a.nrm = h->nrm; a.objpart = h->objpart;
     a.newcnt = h->newcnt; a.scal = h->scal;
     a.old_ptr = h->mm_ptr[o]; a.old_idx = h->mm_idx[o]; a.old_val = h->mm_val[o];
     a.new_ptr = h->mm_ptr[nb];
     a.cnt = h->cnt;
-    a.tmp = h->tmp;
+    a.tmp = h->sc->tmp;
     HIPCHK(h, launch_update_sums(a, s));
     int64_t nnz_new = 0;
-    HIPCHK(h, hipMemcpyAsync(&nnz_new, h->mm_ptr[nb] + h->k, sizeof(int64_t),
-                             hipMemcpyDeviceToHost, s));
-    HIPCHK(h, hipStreamSynchronize(s));
-    ivf_status st = ensure_mm(h, nb, nnz_new);
-    if (st != IVF_OK) return st;
+    if (!h->fixed) {
+        HIPCHK(h, hipMemcpyAsync(&nnz_new, h->mm_ptr[nb] + h->k, sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        ivf_status st = ensure_mm(h, nb, nnz_new);
+        if (st != IVF_OK) return st;
+    }
+    a.new_cap = h->mm_cap[nb];
     a.new_idx = h->mm_idx[nb];
     a.new_val = h->mm_val[nb];
     a.new_row = h->mm_row[nb];
     HIPCHK(h, launch_update_fill(a, s));
     HIPCHK(h, launch_objective_exact(h->objpart, h->k, h->dscal + 1, s));
-    st = rebuild_ivf(h, nb, nnz_new);
+    ivf_status st = rebuild_ivf(h, nb, nnz_new, h->fixed ? h->mm_ptr[nb] + h->k : nullptr);
     if (st != IVF_OK) return st;
     h->cur = nb;
     h->nnzM = nnz_new;
+    h->nnzM_known = !h->fixed;
     h->has_means = true;
-    if (stats) {
+    if (timed) {
         HIPCHK(h, hipEventRecord(h->ev[3], s));
         HIPCHK(h, hipStreamSynchronize(s));
         Counters c;
@@ -294,9 +408,246 @@ ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats) {
         stats->objective_exact = ds[1];
         stats->empty_clusters = (int64_t)c.empty;
         stats->nnz_means = nnz_new;
-        stats->inexact_terms = h->inexact_terms;
+        stats->inexact_terms = h->ov->inexact;
         stats->update_ms = ms;
     }
+    return IVF_OK;
+}
+
+WalkArgs walk_args(ivf_handle* h) {
+    const Plan& p = h->plan;
+    WalkArgs w{};
+    w.x_ptr = h->ov->x_ptr; w.x_idx = h->ov->x_idx; w.x_val = h->ov->x_val; w.n = h->n;
+    w.desc = h->desc; w.post = h->post; w.slab = h->slab;
+    w.k = h->k; w.k_r = p.k_r; w.R = p.R; w.chunk = p.chunk; w.tile_stride = p.tile_stride;
+    w.items_per_range = (h->n + p.chunk - 1) / p.chunk;
+    w.cnt = h->cnt; w.rec = h->rec;
+    return w;
+}
+
+// Assignment step after the walk: merge, FP64 re-score, objective.
+ivf_status assign_finish(ivf_handle* h, int32_t* assign) {
+    const hipStream_t s = h->stream;
+    const Plan& p = h->plan;
+    MergeArgs m{};
+    m.x_ptr = h->ov->x_ptr; m.n = h->n; m.R = p.R;
+    m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
+    m.rec = h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
+    m.best = h->best; m.best_id = h->best_id; m.second = h->second; m.flags = h->flags;
+    m.rescore_list = h->rescore_list; m.cnt = h->cnt;
+    HIPCHK(h, launch_merge(m, s));
+    if (h->opt.certify) {
+        RescoreArgs r{};
+        r.x_ptr = h->ov->x_ptr; r.x_idx = h->ov->x_idx; r.x_val = h->ov->x_val;
+        r.ivf_ptr = h->ivf_ptr; r.cid = h->cid; r.val64 = h->val64;
+        r.k = h->k; r.k_r64 = p.k_r64; r.R64 = p.R64;
+        r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
+        r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
+        HIPCHK(h, launch_rescore(r, h->rescore_grid, s));
+    }
+    HIPCHK(h, launch_objective(h->rho, assign, h->prev, h->n, h->part, kObjBlocks, h->dscal,
+                               h->cnt, s));
+    return IVF_OK;
+}
+
+ivf_status assign_stats(ivf_handle* h, ivf_stats* stats, bool timed) {
+    Counters c;
+    double obj = 0.0;
+    HIPCHK(h, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpy(&obj, h->dscal, sizeof(obj), hipMemcpyDeviceToHost));
+    float ms = 0.f, wms = 0.f;
+    if (timed) {
+        HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+        HIPCHK(h, hipEventElapsedTime(&wms, h->ev[4], h->ev[5]));
+    }
+    double bound, err;
+    std::memcpy(&bound, &c.max_bound_bits, sizeof(double));
+    std::memcpy(&err, &c.max_err_bits, sizeof(double));
+    stats->objective = obj;
+    stats->objective_bound = bound;
+    stats->changed = (int64_t)c.changed;
+    stats->certified = (int64_t)c.certified;
+    stats->rescored = (int64_t)c.n_rescore;
+    stats->zero_overlap = (int64_t)c.zero_overlap;
+    stats->mult_adds = (int64_t)c.mult;
+    stats->max_rel_err = err;
+    stats->assign_ms = ms;
+    stats->walk_ms = wms;
+    stats->objective_exact = std::nan("");
+    stats->empty_clusters = -1;
+    stats->nnz_means = h->nnzM_known ? h->nnzM : -1;
+    stats->inexact_terms = h->ov->inexact;
+    stats->update_ms = 0.f;
+    return IVF_OK;
+}
+
+int occupancy_grid(int cus, const void* kernel, int waves, int lds) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave * waves,
+                                                     (size_t)lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+// Validation, term-major view and fixed-point scales of one object set.
+ivf_status build_objview(ivf_handle* h, const ivf_csr* X) {
+    ObjView* ov = h->ov;
+    ov->x_ptr = X->indptr; ov->x_idx = X->indices; ov->x_val = X->values;
+    ov->n = X->n; ov->d = X->d; ov->nnz = X->nnz;
+    const int64_t n = X->n, d = X->d, nnz = X->nnz;
+    HIPCHK(h, launch_clear_counters(h->cnt, h->stream));
+    ObjectView xv{X->indptr, X->indices, X->values, n, d, nnz};
+    HIPCHK(h, launch_validate_objects(xv, h->cnt, h->stream));
+    ivf_status st = read_errors(h, "objects");
+    if (st != IVF_OK) return st;
+    st = ensure_scratch(h, std::max<int64_t>(nnz, 1));
+    if (st != IVF_OK) return st;
+    Scratch* sc = h->sc;
+    int32_t* rowid = nullptr;
+    HIPCHK(h, dalloc(&rowid, nnz));
+    HIPCHK(h, dalloc(&ov->xt_obj, nnz));
+    HIPCHK(h, dalloc(&ov->xt_term, nnz));
+    HIPCHK(h, dalloc(&ov->xt_val, nnz));
+    if (nnz > 0) {
+        // stable sort of (term, position): positions ascend with objects
+        HIPCHK(h, launch_row_ids(X->indptr, n, rowid, h->stream));
+        HIPCHK(h, launch_copy_keys(X->indices, sc->keys, nnz, h->stream));
+        int bits = 1;
+        while (bits < 31 && ((int64_t)1 << bits) <= d - 1) ++bits;
+        HIPCHK(h, radix_sort_pairs(sc->keys, sc->vals, sc->keys_alt, sc->vals_alt, nnz, bits,
+                                   sc->tmp, h->stream, sc->iota));
+        HIPCHK(h, launch_build_xt(sc->keys, sc->vals, rowid, X->values, nnz, ov->xt_obj,
+                                  ov->xt_term, ov->xt_val, h->stream));
+    }
+    int32_t *emin = nullptr, *emax = nullptr, *tcount = nullptr;
+    HIPCHK(h, dalloc(&emin, d));
+    HIPCHK(h, dalloc(&emax, d));
+    HIPCHK(h, dalloc(&tcount, d));
+    HIPCHK(h, dalloc(&ov->shift, d));
+    HIPCHK(h, launch_term_shift(X->indices, X->values, nnz, d, emin, emax, tcount, ov->shift,
+                                h->cnt, h->stream));
+    Counters c;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    HIPCHK(h, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
+    ov->inexact = (int64_t)c.pad[0];
+    (void)hipFree(rowid);
+    (void)hipFree(emin);
+    (void)hipFree(emax);
+    (void)hipFree(tcount);
+    return IVF_OK;
+}
+
+// Plan-dependent buffers (one range record per object and range, one slice
+// descriptor per term and range).
+ivf_status alloc_plan_buffers(ivf_handle* h) {
+    dfree(h->desc);
+    dfree(h->dsz);
+    dfree(h->rec);
+    HIPCHK(h, dalloc(&h->desc, h->d * (int64_t)h->plan.R));
+    HIPCHK(h, dalloc(&h->dsz, h->d * (int64_t)h->plan.R + 1));
+    HIPCHK(h, dalloc(&h->rec, h->n * (int64_t)h->plan.R));
+    return IVF_OK;
+}
+
+// Everything a handle owns besides the shared view and scratch.
+ivf_status alloc_handle(ivf_handle* h) {
+    const int64_t n = h->n, d = h->d;
+    const int32_t k = h->k;
+    HIPCHK(h, dalloc(&h->size, k));
+    HIPCHK(h, dalloc(&h->cstart, (int64_t)k + 1));
+    HIPCHK(h, dalloc(&h->newcnt, (int64_t)k + 1));
+    HIPCHK(h, dalloc(&h->scal, 4));
+    HIPCHK(h, dalloc(&h->nrm, k));
+    HIPCHK(h, dalloc(&h->objpart, k));
+    for (int b = 0; b < 2; ++b) {
+        HIPCHK(h, dalloc(&h->mm_ptr[b], (int64_t)k + 1));
+        HIPCHK(h, hipMemsetAsync(h->mm_ptr[b], 0, sizeof(int64_t) * ((size_t)k + 1), h->stream));
+    }
+    ivf_status st = ensure_mm(h, 0, 1);
+    if (st != IVF_OK) return st;
+    st = ensure_mm(h, 1, 1);
+    if (st != IVF_OK) return st;
+    HIPCHK(h, dalloc(&h->ivf_ptr, d + 1));
+    st = alloc_plan_buffers(h);
+    if (st != IVF_OK) return st;
+    st = ensure_ivf(h, 1);
+    if (st != IVF_OK) return st;
+    HIPCHK(h, dalloc(&h->prev, n));
+    HIPCHK(h, dalloc(&h->seed_assign, n));
+    HIPCHK(h, dalloc(&h->rho, n));
+    HIPCHK(h, dalloc(&h->best, n));
+    HIPCHK(h, dalloc(&h->second, n));
+    HIPCHK(h, dalloc(&h->best_id, n));
+    HIPCHK(h, dalloc(&h->flags, n));
+    HIPCHK(h, dalloc(&h->rescore_list, n));
+    HIPCHK(h, dalloc(&h->part, kObjBlocks));
+    HIPCHK(h, dalloc(&h->dscal, 4));
+    HIPCHK(h, walk_set_lds_limit(kLdsBytes));
+    h->walk_grid = occupancy_grid(h->cus, walk_kernel_ptr(h->opt.valtype), h->plan.waves,
+                                  h->plan.lds_bytes);
+    h->rescore_grid = h->cus * 2;
+    return IVF_OK;
+}
+
+ivf_status check_csr(const ivf_csr* X, int32_t k) {
+    if (!X) return fail(nullptr, IVF_ERR_ARG, "null argument");
+    if (X->n < 1 || X->d < 1 || X->nnz < 0) return fail(nullptr, IVF_ERR_ARG, "bad sizes");
+    if (!X->indptr || (X->nnz > 0 && (!X->indices || !X->values)))
+        return fail(nullptr, IVF_ERR_ARG, "null object arrays");
+    if (k < 1 || (int64_t)k > X->n) return fail(nullptr, IVF_ERR_ARG, "k outside [1, n]");
+    if (k >= (1 << 24)) return fail(nullptr, IVF_ERR_CAPACITY, "k >= 2^24");
+    if (X->nnz >= ((int64_t)1 << 31) - 1 || X->n >= ((int64_t)1 << 31) - 1 ||
+        X->d >= ((int64_t)1 << 31) - 1)
+        return fail(nullptr, IVF_ERR_CAPACITY, "n, d or nnz >= 2^31");
+    return IVF_OK;
+}
+
+// A handle on X with k clusters.  sc / ov: shared scratch and view, or null
+// to create owned ones.
+ivf_status create_handle(const ivf_csr* X, int32_t k, const ivf_options& o, Scratch* sc,
+                         ObjView* ov, ivf_handle** out) {
+    *out = nullptr;
+    Plan plan;
+    std::string perr;
+    ivf_status pst = make_plan(k, &o, &plan, &perr);
+    if (pst != IVF_OK) return fail(nullptr, pst, perr);
+    ivf_handle* h = new (std::nothrow) ivf_handle();
+    if (!h) return fail(nullptr, IVF_ERR_OOM, "host allocation failed");
+    h->n = X->n; h->d = X->d; h->nnz = X->nnz; h->k = k;
+    h->opt = o;
+    h->stream = reinterpret_cast<hipStream_t>(o.stream);
+    h->plan = plan;
+    h->sc = sc ? sc : new (std::nothrow) Scratch();
+    h->owns_sc = !sc;
+    h->ov = ov ? ov : new (std::nothrow) ObjView();
+    h->owns_ov = !ov;
+    auto bail = [&](ivf_status st) {
+        g_build_error = h->err;
+        free_handle(h);
+        delete h;
+        return st;
+    };
+    if (!h->sc || !h->ov) return bail(fail(h, IVF_ERR_OOM, "host allocation failed"));
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    for (auto& ev : h->ev)
+        if (e == hipSuccess) e = hipEventCreate(&ev);
+    if (e == hipSuccess) e = dalloc(&h->cnt, 1);
+    if (e == hipSuccess) e = launch_clear_counters(h->cnt, h->stream);
+    if (e != hipSuccess)
+        return bail(fail(h, e == hipErrorOutOfMemory ? IVF_ERR_OOM : IVF_ERR_HIP,
+                         std::string("device setup: ") + hipGetErrorString(e)));
+    ivf_status st = IVF_OK;
+    if (!ov) st = build_objview(h, X);
+    else st = ensure_scratch(h, std::max<int64_t>(X->nnz, 1));
+    if (st == IVF_OK) st = alloc_handle(h);
+    if (st == IVF_OK) {
+        e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) st = fail(h, IVF_ERR_HIP, hipGetErrorString(e));
+    }
+    if (st != IVF_OK) return bail(st);
+    *out = h;
     return IVF_OK;
 }
 
@@ -343,6 +694,233 @@ ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err)
 }
 
 }  // namespace ivf
+
+// ------------------------------------------------------------------ batches
+struct ivf_batch {
+    std::vector<ivf_handle*> h;
+    std::vector<ObjView*> views;
+    Scratch* sc = nullptr;
+    ivf_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cus = 0;
+    int32_t kr_max = 0, waves = 0, tile_stride = 0, grid = 0;
+    bool tuned = false;
+    WalkArgs* d_args = nullptr;
+    int64_t* d_item_off = nullptr;
+    Counters** d_cnt = nullptr;                // every instance's counters
+    unsigned long long* d_flags = nullptr;     // their error flags, gathered
+    // two recorded iterations: every instance's means move from its current
+    // buffer to the other in exec[0] and back in exec[1]; phase: the next one
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    int phase = 0;
+    std::vector<int32_t*> captured_assign;
+    int eager_left = 2;      // eager iterations that size the fixed capacities
+    double slack_frac = 0.5;  // fixed capacity = need * (1 + slack_frac) + slack_abs
+    int64_t slack_abs = 1024;
+    int32_t recoveries = 0;   // replays whose new means overflowed a fixed capacity
+    int32_t captures = 0;     // times the iteration was recorded
+    std::vector<float> tune_ms;   // autotuner: walk time of each candidate tried
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+namespace {
+
+ivf_status bfail(ivf_batch* b, ivf_status st, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_build_error = msg;
+    return st;
+}
+
+#define BHIP(b, call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return bfail((b), e_ == hipErrorOutOfMemory ? IVF_ERR_OOM : IVF_ERR_HIP,     \
+                         std::string(#call) + ": " + hipGetErrorString(e_));             \
+    } while (0)
+
+void drop_graphs(ivf_batch* b) {
+    for (auto& e : b->exec)
+        if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+}
+
+ivf_status upload_args(ivf_batch* b) {
+    const int32_t count = (int32_t)b->h.size();
+    std::vector<WalkArgs> args(count);
+    std::vector<int64_t> off(count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        args[i] = walk_args(b->h[i]);
+        off[i + 1] = off[i] + args[i].items_per_range * args[i].R;
+    }
+    BHIP(b, hipMemcpyAsync(b->d_args, args.data(), sizeof(WalkArgs) * count,
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_item_off, off.data(), sizeof(int64_t) * (count + 1),
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return IVF_OK;
+}
+
+// Re-plan every instance for (kr_max, waves); with means present, their
+// inverted files are rebuilt for the new ranges.
+ivf_status batch_plan(ivf_batch* b, int32_t kr_max, int32_t waves) {
+    ivf_options o = b->opt;
+    o.cluster_range = kr_max;
+    o.waves_per_wg = 1;   // per-instance tiles are unused by the batched walk
+    int32_t stride = 4;
+    std::vector<Plan> plans;
+    for (ivf_handle* h : b->h) {
+        Plan p;
+        std::string perr;
+        ivf_status st = make_plan(h->k, &o, &p, &perr);
+        if (st != IVF_OK) return bfail(b, st, perr);
+        stride = std::max(stride, p.tile_stride);
+        plans.push_back(p);
+    }
+    if ((int64_t)waves * stride * 4 > kLdsBytes) return bfail(b, IVF_ERR_ARG, "tiles exceed LDS");
+    for (size_t i = 0; i < b->h.size(); ++i) {
+        ivf_handle* h = b->h[i];
+        const bool new_ranges = plans[i].R != h->plan.R;
+        h->plan = plans[i];
+        if (new_ranges) {
+            ivf_status st = alloc_plan_buffers(h);
+            if (st != IVF_OK) return bfail(b, st, h->err);
+        }
+        ivf_status st = ensure_scratch(h, std::max<int64_t>(h->nnz, 1));
+        if (st != IVF_OK) return bfail(b, st, h->err);
+        if (h->has_means) {
+            if (!h->nnzM_known) {
+                BHIP(b, hipStreamSynchronize(b->stream));
+                BHIP(b, hipMemcpy(&h->nnzM, h->mm_ptr[h->cur] + h->k, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost));
+                h->nnzM_known = true;
+            }
+            st = rebuild_ivf(h, h->cur, h->nnzM, nullptr);
+            if (st != IVF_OK) return bfail(b, st, h->err);
+        }
+    }
+    b->kr_max = kr_max;
+    b->waves = waves;
+    b->tile_stride = stride;
+    b->grid = occupancy_grid(b->cus, walk_batch_kernel_ptr(b->opt.valtype), waves,
+                             waves * stride * 4);
+    drop_graphs(b);
+    return upload_args(b);
+}
+
+// Autotuner: time the batched walk on the current means for every candidate
+// (clusters per tile, waves per workgroup) and keep the fastest.
+ivf_status batch_autotune(ivf_batch* b) {
+    static const int32_t cand[][2] = {{640, 8}, {1280, 8}, {1280, 4}, {2560, 4}, {2560, 8}};
+    const int32_t count = (int32_t)b->h.size();
+    float best = 1e30f;
+    int bi = 1;
+    b->tune_ms.clear();
+    for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])); ++c) {
+        ivf_status st = batch_plan(b, cand[c][0], cand[c][1]);
+        if (st != IVF_OK) return st;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {   // the first launch warms the caches
+            BHIP(b, hipEventRecord(b->ev[0], b->stream));
+            BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, count, b->tile_stride,
+                                      b->opt.valtype, b->waves, b->grid, b->stream));
+            BHIP(b, hipEventRecord(b->ev[1], b->stream));
+            BHIP(b, hipEventSynchronize(b->ev[1]));
+            BHIP(b, hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+        }
+        b->tune_ms.push_back(ms);
+        if (ms < best) { best = ms; bi = c; }
+    }
+    b->tuned = true;
+    return batch_plan(b, cand[bi][0], cand[bi][1]);
+}
+
+// One Lloyd iteration of every instance.  Eager (synchronises, may grow
+// buffers) or, with every handle fixed, recordable in a graph.
+ivf_status batch_iteration(ivf_batch* b, int32_t* const* assign, bool eager) {
+    const hipStream_t s = b->stream;
+    const int32_t count = (int32_t)b->h.size();
+    for (int32_t i = 0; i < count; ++i) {
+        ivf_handle* h = b->h[i];
+        HIPCHK(h, launch_clear_counters(h->cnt, s));
+        HIPCHK(h, hipMemcpyAsync(h->prev, assign[i], sizeof(int32_t) * (size_t)h->n,
+                                 hipMemcpyDeviceToDevice, s));
+    }
+    BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, count, b->tile_stride, b->opt.valtype,
+                              b->waves, b->grid, s));
+    for (int32_t i = 0; i < count; ++i) {
+        ivf_status st = assign_finish(b->h[i], assign[i]);
+        if (st != IVF_OK) return bfail(b, st, b->h[i]->err);
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        ivf_status st = run_update(b->h[i], assign[i], nullptr, false);
+        if (st != IVF_OK) return bfail(b, st, b->h[i]->err);
+    }
+    if (eager) return upload_args(b);   // slab pointers may have moved
+    return IVF_OK;
+}
+
+ivf_status batch_fix_capacities(ivf_batch* b) {
+    // capacities: what the eager iterations needed plus the slack; slices that
+    // would not fit a slab later stay sparse, means that would not fit are flagged
+    BHIP(b, hipStreamSynchronize(b->stream));
+    for (ivf_handle* h : b->h) {
+        h->fixed = false;
+        if (!h->nnzM_known) {   // after replays the count lives on the device
+            BHIP(b, hipMemcpy(&h->nnzM, h->mm_ptr[h->cur] + h->k, sizeof(int64_t),
+                              hipMemcpyDeviceToHost));
+            h->nnzM_known = true;
+        }
+        const int64_t need = std::max<int64_t>(h->nnzM, 1);
+        const int64_t cap = need + (int64_t)((double)need * b->slack_frac) + b->slack_abs;
+        for (int m = 0; m < 2; ++m) {   // the current means are carried over
+            ivf_status st = ensure_mm(h, m, cap, m == h->cur ? h->nnzM : 0);
+            if (st != IVF_OK) return bfail(b, st, h->err);
+        }
+        ivf_status st = ensure_ivf(h, std::max(h->mm_cap[0], h->mm_cap[1]));
+        if (st != IVF_OK) return bfail(b, st, h->err);
+        st = ensure_slab(h, h->slab_need + (int64_t)((double)h->slab_need * b->slack_frac) +
+                                b->slack_abs);
+        if (st != IVF_OK) return bfail(b, st, h->err);
+        // the inverted file and slabs may have been reallocated: rebuild them
+        st = rebuild_ivf(h, h->cur, h->nnzM, nullptr);
+        if (st != IVF_OK) return bfail(b, st, h->err);
+    }
+    for (ivf_handle* h : b->h) h->fixed = true;
+    drop_graphs(b);
+    return upload_args(b);
+}
+
+ivf_status batch_capture(ivf_batch* b, int32_t* const* assign) {
+    drop_graphs(b);
+    for (int g = 0; g < 2; ++g) {
+        hipGraph_t graph = nullptr;
+        BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        ivf_status st = batch_iteration(b, assign, false);
+        hipError_t ee = hipStreamEndCapture(b->stream, &graph);
+        if (st != IVF_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        BHIP(b, ee);
+        hipError_t ei = hipGraphInstantiate(&b->exec[g], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        BHIP(b, ei);
+    }
+    // recording flipped every handle's buffer parity twice: back where it was
+    b->captured_assign.assign(assign, assign + b->h.size());
+    b->phase = 0;
+    ++b->captures;
+    return IVF_OK;
+}
+
+__global__ void k_gather_flags(Counters* const* cnts, int32_t count, unsigned long long* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = cnts[i]->error_flags;
+}
+
+}  // namespace
 
 // --------------------------------------------------------------------- C ABI
 extern "C" {
@@ -399,152 +977,22 @@ ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]) {
 
 ivf_status ivf_build(const ivf_csr* X, int32_t k, const ivf_options* opts, ivf_handle** out) {
     if (out) *out = nullptr;
-    if (!X || !out) return fail(nullptr, IVF_ERR_ARG, "null argument");
-    if (X->n < 1 || X->d < 1 || X->nnz < 0) return fail(nullptr, IVF_ERR_ARG, "bad sizes");
-    if (!X->indptr || (X->nnz > 0 && (!X->indices || !X->values)))
-        return fail(nullptr, IVF_ERR_ARG, "null object arrays");
-    if (k < 1 || (int64_t)k > X->n) return fail(nullptr, IVF_ERR_ARG, "k outside [1, n]");
-    if (k >= (1 << 24)) return fail(nullptr, IVF_ERR_CAPACITY, "k >= 2^24");
-    if (X->nnz >= ((int64_t)1 << 31) - 1 || X->n >= ((int64_t)1 << 31) - 1 ||
-        X->d >= ((int64_t)1 << 31) - 1)
-        return fail(nullptr, IVF_ERR_CAPACITY, "n, d or nnz >= 2^31");
+    if (!out) return fail(nullptr, IVF_ERR_ARG, "null argument");
+    ivf_status st = check_csr(X, k);
+    if (st != IVF_OK) return st;
     ivf_options o;
     ivf_default_options(&o);
     if (opts) o = *opts;
     if (o.valtype < IVF_VAL_F32 || o.valtype > IVF_VAL_F16)
         return fail(nullptr, IVF_ERR_ARG, "unknown valtype");
-    Plan plan;
-    std::string perr;
-    ivf_status pst = make_plan(k, &o, &plan, &perr);
-    if (pst != IVF_OK) return fail(nullptr, pst, perr);
-
-    ivf_handle* h = new (std::nothrow) ivf_handle();
-    if (!h) return fail(nullptr, IVF_ERR_OOM, "host allocation failed");
-    h->n = X->n; h->d = X->d; h->nnz = X->nnz; h->k = k;
-    h->opt = o;
-    h->stream = reinterpret_cast<hipStream_t>(o.stream);
-    h->plan = plan;
-    h->x_ptr = X->indptr; h->x_idx = X->indices; h->x_val = X->values;
-    auto bail = [&](ivf_status st) {
-        g_build_error = h->err;
-        free_all(h);
-        delete h;
-        return st;
-    };
-#define BCHK(call)                                                                         \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return bail(fail(h, e_ == hipErrorOutOfMemory ? IVF_ERR_OOM : IVF_ERR_HIP,     \
-                             std::string(#call) + ": " + hipGetErrorString(e_)));          \
-    } while (0)
-#define BST(expr)                            \
-    do {                                     \
-        ivf_status s_ = (expr);              \
-        if (s_ != IVF_OK) return bail(s_);   \
-    } while (0)
-
-    BCHK(hipGetDevice(&h->device));
-    BCHK(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device));
-    for (auto& e : h->ev) BCHK(hipEventCreate(&e));
-    BCHK(dalloc(&h->cnt, 1));
-    BCHK(launch_clear_counters(h->cnt, h->stream));
-    // validation before anything else reads the objects
-    ObjectView xv{X->indptr, X->indices, X->values, X->n, X->d, X->nnz};
-    BCHK(launch_validate_objects(xv, h->cnt, h->stream));
-    BST(read_errors(h, "objects"));
-
-    const int64_t n = h->n, d = h->d, nnz = h->nnz;
-    BST(ensure_sort(h, std::max<int64_t>(nnz, 1)));
-    // term-major view: stable sort of (term, position), positions ascend with objects
-    int32_t* rowid = nullptr;
-    BCHK(dalloc(&rowid, nnz));
-    BCHK(dalloc(&h->xt_obj, nnz));
-    BCHK(dalloc(&h->xt_term, nnz));
-    BCHK(dalloc(&h->xt_val, nnz));
-    if (nnz > 0) {
-        BCHK(launch_row_ids(X->indptr, n, rowid, h->stream));
-        BCHK(launch_copy_keys(X->indices, h->keys, nnz, h->stream));
-        int bits = 1;
-        while (bits < 31 && ((int64_t)1 << bits) <= d - 1) ++bits;
-        BCHK(radix_sort_pairs(h->keys, h->vals, h->keys_alt, h->vals_alt, nnz, bits, h->tmp,
-                              h->stream, h->iota));
-        BCHK(launch_build_xt(h->keys, h->vals, rowid, X->values, nnz, h->xt_obj, h->xt_term,
-                             h->xt_val, h->stream));
-    }
-    // per-term fixed-point scales of the member sums
-    int32_t *emin = nullptr, *emax = nullptr, *tcount = nullptr;
-    BCHK(dalloc(&emin, d));
-    BCHK(dalloc(&emax, d));
-    BCHK(dalloc(&tcount, d));
-    BCHK(dalloc(&h->shift, d));
-    BCHK(launch_term_shift(X->indices, X->values, nnz, d, emin, emax, tcount, h->shift, h->cnt,
-                           h->stream));
-    {
-        Counters c;
-        BCHK(hipStreamSynchronize(h->stream));
-        BCHK(hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
-        h->inexact_terms = (int64_t)c.pad[0];
-    }
-    (void)hipFree(rowid);
-    (void)hipFree(emin);
-    (void)hipFree(emax);
-    (void)hipFree(tcount);
-    // segment and cluster scratch
-    BCHK(dalloc(&h->flag, nnz));
-    BCHK(dalloc(&h->segpos, nnz));
-    BCHK(dalloc(&h->seg_acc, nnz));
-    BCHK(dalloc(&h->seg_j, nnz));
-    BCHK(dalloc(&h->seg_t, nnz));
-    BCHK(dalloc(&h->size, k));
-    BCHK(dalloc(&h->cstart, (int64_t)k + 1));
-    BCHK(dalloc(&h->newcnt, (int64_t)k + 1));
-    BCHK(dalloc(&h->scal, 4));
-    BCHK(dalloc(&h->nrm, k));
-    BCHK(dalloc(&h->objpart, k));
-    for (int b = 0; b < 2; ++b) {
-        BCHK(dalloc(&h->mm_ptr[b], (int64_t)k + 1));
-        BCHK(hipMemsetAsync(h->mm_ptr[b], 0, sizeof(int64_t) * ((size_t)k + 1), h->stream));
-    }
-    BST(ensure_mm(h, 0, 1));
-    BST(ensure_mm(h, 1, 1));
-    BCHK(dalloc(&h->ivf_ptr, d + 1));
-    BCHK(dalloc(&h->desc, d * (int64_t)plan.R));
-    BCHK(dalloc(&h->dsz, d * (int64_t)plan.R + 1));
-    BST(ensure_ivf(h, 1));
-    // assignment scratch
-    BCHK(dalloc(&h->rec, n * (int64_t)plan.R));
-    BCHK(dalloc(&h->prev, n));
-    BCHK(dalloc(&h->seed_assign, n));
-    BCHK(dalloc(&h->rho, n));
-    BCHK(dalloc(&h->best, n));
-    BCHK(dalloc(&h->second, n));
-    BCHK(dalloc(&h->best_id, n));
-    BCHK(dalloc(&h->flags, n));
-    BCHK(dalloc(&h->rescore_list, n));
-    BCHK(dalloc(&h->part, kObjBlocks));
-    BCHK(dalloc(&h->dscal, 4));
-    // launch shapes
-    BCHK(walk_set_lds_limit(std::max(plan.lds_bytes, 1)));
-    int per_cu = 0;
-    BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, walk_kernel_ptr(o.valtype), kWave * plan.waves,
-        (size_t)plan.lds_bytes));
-    if (per_cu < 1) per_cu = 1;
-    h->walk_grid = h->cus * per_cu;
-    h->rescore_grid = h->cus * 2;
-    BCHK(hipStreamSynchronize(h->stream));
-#undef BCHK
-#undef BST
-    *out = h;
-    return IVF_OK;
+    return create_handle(X, k, o, nullptr, nullptr, out);
 }
 
 void ivf_destroy(ivf_handle* h) {
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
-    free_all(h);
+    free_handle(h);
     delete h;
 }
 
@@ -555,6 +1003,7 @@ ivf_status ivf_set_means(ivf_handle* h, const ivf_means* M) {
     if (!M->indptr || (M->nnz > 0 && (!M->indices || !M->values)))
         return fail(h, IVF_ERR_ARG, "null mean arrays");
     if (M->nnz >= ((int64_t)1 << 31) - 1) return fail(h, IVF_ERR_CAPACITY, "nnz >= 2^31");
+    if (h->fixed) return fail(h, IVF_ERR_STATE, "capacities are fixed");
     HIPCHK(h, launch_clear_counters(h->cnt, h->stream));
     HIPCHK(h, launch_validate_means(M->indptr, M->indices, M->values, h->k, h->d, M->nnz, h->cnt,
                                     h->stream));
@@ -572,9 +1021,10 @@ ivf_status ivf_set_means(ivf_handle* h, const ivf_means* M) {
                                  hipMemcpyDeviceToDevice, h->stream));
     }
     HIPCHK(h, launch_mean_rows(h->mm_ptr[b], h->k, h->mm_row[b], h->stream));
-    st = rebuild_ivf(h, b, M->nnz);
+    st = rebuild_ivf(h, b, M->nnz, nullptr);
     if (st != IVF_OK) return st;
     h->nnzM = M->nnz;
+    h->nnzM_known = true;
     h->has_means = true;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return IVF_OK;
@@ -582,6 +1032,7 @@ ivf_status ivf_set_means(ivf_handle* h, const ivf_means* M) {
 
 ivf_status ivf_init_seeds(ivf_handle* h, const int32_t* seeds) {
     if (!h || !seeds) return fail(h, IVF_ERR_ARG, "null argument");
+    if (h->fixed) return fail(h, IVF_ERR_STATE, "capacities are fixed");
     // start from empty means so that the singleton update defines every mean
     HIPCHK(h, hipMemsetAsync(h->mm_ptr[h->cur], 0, sizeof(int64_t) * ((size_t)h->k + 1),
                              h->stream));
@@ -601,62 +1052,16 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
     HIPCHK(h, launch_clear_counters(h->cnt, s));
     HIPCHK(h, hipMemcpyAsync(h->prev, assign, sizeof(int32_t) * (size_t)h->n,
                              hipMemcpyDeviceToDevice, s));
-    WalkArgs w{};
-    w.x_ptr = h->x_ptr; w.x_idx = h->x_idx; w.x_val = h->x_val; w.n = h->n;
-    w.desc = h->desc; w.post = h->post; w.slab = h->slab;
-    w.k = h->k; w.k_r = p.k_r; w.R = p.R; w.chunk = p.chunk; w.tile_stride = p.tile_stride;
-    w.items_per_range = (h->n + p.chunk - 1) / p.chunk;
-    w.cnt = h->cnt; w.rec = h->rec;
+    const WalkArgs w = walk_args(h);
     if (stats) HIPCHK(h, hipEventRecord(h->ev[4], s));
     HIPCHK(h, launch_walk(w, h->opt.valtype, p.waves, p.lds_bytes, h->walk_grid, s));
     if (stats) HIPCHK(h, hipEventRecord(h->ev[5], s));
-    MergeArgs m{};
-    m.x_ptr = h->x_ptr; m.n = h->n; m.R = p.R;
-    m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
-    m.rec = h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
-    m.best = h->best; m.best_id = h->best_id; m.second = h->second; m.flags = h->flags;
-    m.rescore_list = h->rescore_list; m.cnt = h->cnt;
-    HIPCHK(h, launch_merge(m, s));
-    if (h->opt.certify) {
-        RescoreArgs r{};
-        r.x_ptr = h->x_ptr; r.x_idx = h->x_idx; r.x_val = h->x_val;
-        r.ivf_ptr = h->ivf_ptr; r.cid = h->cid; r.val64 = h->val64;
-        r.k = h->k; r.k_r64 = p.k_r64; r.R64 = p.R64;
-        r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
-        r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
-        HIPCHK(h, launch_rescore(r, h->rescore_grid, s));
-    }
-    HIPCHK(h, launch_objective(h->rho, assign, h->prev, h->n, h->part, kObjBlocks, h->dscal, h->cnt,
-                               s));
+    ivf_status st = assign_finish(h, assign);
+    if (st != IVF_OK) return st;
     if (stats) {
         HIPCHK(h, hipEventRecord(h->ev[1], s));
         HIPCHK(h, hipStreamSynchronize(s));
-        Counters c;
-        double obj = 0.0;
-        HIPCHK(h, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
-        HIPCHK(h, hipMemcpy(&obj, h->dscal, sizeof(obj), hipMemcpyDeviceToHost));
-        float ms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-        float wms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&wms, h->ev[4], h->ev[5]));
-        double bound, err;
-        std::memcpy(&bound, &c.max_bound_bits, sizeof(double));
-        std::memcpy(&err, &c.max_err_bits, sizeof(double));
-        stats->objective = obj;
-        stats->objective_bound = bound;
-        stats->changed = (int64_t)c.changed;
-        stats->certified = (int64_t)c.certified;
-        stats->rescored = (int64_t)c.n_rescore;
-        stats->zero_overlap = (int64_t)c.zero_overlap;
-        stats->mult_adds = (int64_t)c.mult;
-        stats->max_rel_err = err;
-        stats->assign_ms = ms;
-        stats->walk_ms = wms;
-        stats->objective_exact = std::nan("");
-        stats->empty_clusters = -1;
-        stats->nnz_means = h->nnzM;
-        stats->inexact_terms = h->inexact_terms;
-        stats->update_ms = 0.f;
+        return assign_stats(h, stats, true);
     }
     return IVF_OK;
 }
@@ -681,6 +1086,13 @@ ivf_status ivf_iterate(ivf_handle* h, int32_t iters, int32_t* assign, ivf_stats*
 ivf_status ivf_get_means(ivf_handle* h, ivf_means* out) {
     if (!h || !out) return fail(h, IVF_ERR_ARG, "null argument");
     if (!h->has_means) return fail(h, IVF_ERR_STATE, "no means yet");
+    const int b = h->cur;
+    if (!h->nnzM_known) {
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipMemcpy(&h->nnzM, h->mm_ptr[b] + h->k, sizeof(int64_t),
+                            hipMemcpyDeviceToHost));
+        h->nnzM_known = true;
+    }
     out->k = h->k;
     out->d = h->d;
     if (!out->indptr) {
@@ -689,7 +1101,6 @@ ivf_status ivf_get_means(ivf_handle* h, ivf_means* out) {
     }
     if (out->nnz < h->nnzM || (h->nnzM > 0 && (!out->indices || !out->values)))
         return fail(h, IVF_ERR_ARG, "output buffers smaller than nnz");
-    const int b = h->cur;
     HIPCHK(h, hipMemcpyAsync(out->indptr, h->mm_ptr[b], sizeof(int64_t) * ((size_t)h->k + 1),
                              hipMemcpyDeviceToDevice, h->stream));
     if (h->nnzM > 0) {
@@ -716,6 +1127,250 @@ ivf_status ivf_get_scores(ivf_handle* h, float* best, int32_t* best_id, float* s
     if (flags) HIPCHK(h, hipMemcpyAsync(flags, h->flags, n, hipMemcpyDeviceToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return IVF_OK;
+}
+
+// ------------------------------------------------------------------ batches
+void ivf_batch_destroy(ivf_batch* b);
+
+ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
+                           const ivf_options* opts, ivf_batch** out) {
+    if (out) *out = nullptr;
+    if (!out || !X || !k || count < 1) return bfail(nullptr, IVF_ERR_ARG, "bad argument");
+    for (int32_t i = 0; i < count; ++i) {
+        ivf_status st = check_csr(&X[i], k[i]);
+        if (st != IVF_OK) return st;
+    }
+    ivf_options o;
+    ivf_default_options(&o);
+    if (opts) o = *opts;
+    if (o.valtype < IVF_VAL_F32 || o.valtype > IVF_VAL_F16)
+        return bfail(nullptr, IVF_ERR_ARG, "unknown valtype");
+    ivf_batch* b = new (std::nothrow) ivf_batch();
+    if (!b) return bfail(nullptr, IVF_ERR_OOM, "host allocation failed");
+    auto bail = [&](ivf_status st) {
+        const std::string msg = b->err;
+        ivf_batch_destroy(b);
+        g_build_error = msg;
+        return st;
+    };
+    b->opt = o;
+    // graph capture needs a stream of its own (never the null stream)
+    if (o.stream) {
+        b->stream = reinterpret_cast<hipStream_t>(o.stream);
+    } else {
+        BHIP(b, hipStreamCreate(&b->stream));
+        b->own_stream = true;
+    }
+    b->opt.stream = b->stream;
+    int dev = 0;
+    BHIP(b, hipGetDevice(&dev));
+    BHIP(b, hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    b->sc = new (std::nothrow) Scratch();
+    if (!b->sc) return bail(bfail(b, IVF_ERR_OOM, "host allocation failed"));
+    // the shared scratch is sized for the largest instance up front
+    int64_t maxnnz = 1;
+    for (int32_t i = 0; i < count; ++i) maxnnz = std::max(maxnnz, X[i].nnz);
+    BHIP(b, b->sc->ensure(maxnnz, maxnnz, 1, b->stream));
+    ivf_options oi = b->opt;
+    oi.cluster_range = o.cluster_range > 0 ? o.cluster_range : 1280;
+    oi.waves_per_wg = 1;
+    for (int32_t i = 0; i < count; ++i) {
+        ObjView* ov = nullptr;
+        for (int32_t j = 0; j < i; ++j)   // instances on the same object set share its view
+            if (X[j].indptr == X[i].indptr && X[j].indices == X[i].indices &&
+                X[j].values == X[i].values && X[j].n == X[i].n && X[j].d == X[i].d &&
+                X[j].nnz == X[i].nnz)
+                ov = b->h[j]->ov;
+        ivf_handle* h = nullptr;
+        ivf_status st = create_handle(&X[i], k[i], oi, b->sc, ov, &h);
+        if (st != IVF_OK) return bail(bfail(b, st, g_build_error));
+        h->owns_sc = false;
+        if (!ov) {   // the batch owns every view; handles only borrow
+            h->owns_ov = false;
+            b->views.push_back(h->ov);
+        }
+        b->h.push_back(h);
+    }
+    BHIP(b, dalloc(&b->d_args, count));
+    BHIP(b, dalloc(&b->d_item_off, count + 1));
+    BHIP(b, dalloc(&b->d_flags, count));
+    BHIP(b, dalloc(&b->d_cnt, count));
+    {
+        std::vector<Counters*> cp(count);
+        for (int32_t i = 0; i < count; ++i) cp[i] = b->h[i]->cnt;
+        BHIP(b, hipMemcpy(b->d_cnt, cp.data(), sizeof(Counters*) * count, hipMemcpyHostToDevice));
+    }
+    for (auto& e : b->ev) BHIP(b, hipEventCreate(&e));
+    ivf_status st = batch_plan(b, oi.cluster_range, o.waves_per_wg > 0 ? o.waves_per_wg : 8);
+    if (st != IVF_OK) return bail(st);
+    *out = b;
+    return IVF_OK;
+}
+
+ivf_status ivf_batch_init_seeds(ivf_batch* b, const int32_t* const* seeds) {
+    if (!b || !seeds) return bfail(b, IVF_ERR_ARG, "null argument");
+    for (size_t i = 0; i < b->h.size(); ++i) {
+        ivf_status st = ivf_init_seeds(b->h[i], seeds[i]);
+        if (st != IVF_OK) return bfail(b, st, b->h[i]->err);
+    }
+    return upload_args(b);
+}
+
+ivf_status ivf_batch_set_means(ivf_batch* b, int32_t inst, const ivf_means* M) {
+    if (!b || inst < 0 || inst >= (int32_t)b->h.size()) return bfail(b, IVF_ERR_ARG, "bad instance");
+    ivf_status st = ivf_set_means(b->h[inst], M);
+    if (st != IVF_OK) return bfail(b, st, b->h[inst]->err);
+    return upload_args(b);
+}
+
+ivf_status ivf_batch_iterate(ivf_batch* b, int32_t iters, int32_t* const* assign,
+                             ivf_stats* stats) {
+    if (!b || !assign || iters < 0) return bfail(b, IVF_ERR_ARG, "bad argument");
+    const int32_t count = (int32_t)b->h.size();
+    for (ivf_handle* h : b->h)
+        if (!h->has_means) return bfail(b, IVF_ERR_STATE, "instance without means");
+    for (int32_t r = 0; r < iters; ++r) {
+        const bool eager = b->eager_left > 0;
+        float ms = 0.f;
+        if (eager) {
+            for (ivf_handle* h : b->h) h->fixed = false;
+            BHIP(b, hipEventRecord(b->ev[0], b->stream));
+            ivf_status st = batch_iteration(b, assign, true);
+            if (st != IVF_OK) return st;
+            BHIP(b, hipEventRecord(b->ev[1], b->stream));
+            BHIP(b, hipEventSynchronize(b->ev[1]));
+            BHIP(b, hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            if (--b->eager_left == 0) {
+                if (!b->tuned && b->opt.cluster_range == 0) {
+                    st = batch_autotune(b);
+                    if (st != IVF_OK) return st;
+                }
+                st = batch_fix_capacities(b);
+                if (st != IVF_OK) return st;
+            }
+        } else {
+            bool same = b->exec[0] && b->exec[1] && b->captured_assign.size() == (size_t)count;
+            for (int32_t i = 0; same && i < count; ++i) same = b->captured_assign[i] == assign[i];
+            if (!same) {
+                ivf_status st = batch_capture(b, assign);
+                if (st != IVF_OK) return st;
+            }
+            BHIP(b, hipEventRecord(b->ev[0], b->stream));
+            BHIP(b, hipGraphLaunch(b->exec[b->phase], b->stream));
+            b->phase ^= 1;
+            BHIP(b, hipEventRecord(b->ev[1], b->stream));
+            for (ivf_handle* h : b->h) {
+                h->cur = 1 - h->cur;
+                h->nnzM_known = false;
+            }
+            k_gather_flags<<<(count + 63) / 64, 64, 0, b->stream>>>(b->d_cnt, count, b->d_flags);
+            std::vector<unsigned long long> fl(count);
+            BHIP(b, hipMemcpyAsync(fl.data(), b->d_flags, sizeof(unsigned long long) * count,
+                                   hipMemcpyDeviceToHost, b->stream));
+            BHIP(b, hipStreamSynchronize(b->stream));
+            BHIP(b, hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+            // a fixed capacity was exceeded: the old means are intact, so that
+            // update is redone eagerly with growth, then the graphs re-recorded
+            bool redo = false;
+            for (int32_t i = 0; i < count; ++i) {
+                if (!(fl[i] & kOverflow)) continue;
+                ivf_handle* h = b->h[i];
+                h->cur = 1 - h->cur;
+                h->fixed = false;
+                // the update's own counters start again; the assignment's stay
+                BHIP(b, hipMemsetAsync(&h->cnt->empty, 0, sizeof(unsigned long long), b->stream));
+                BHIP(b, hipMemsetAsync(&h->cnt->error_flags, 0, sizeof(unsigned long long),
+                                       b->stream));
+                ivf_status st = run_update(h, assign[i], nullptr, false);
+                if (st != IVF_OK) return bfail(b, st, h->err);
+                redo = true;
+            }
+            if (redo) {
+                ++b->recoveries;
+                ivf_status st = batch_fix_capacities(b);
+                if (st != IVF_OK) return st;
+            }
+        }
+        if (stats) {
+            BHIP(b, hipStreamSynchronize(b->stream));
+            for (int32_t i = 0; i < count; ++i) {
+                ivf_handle* h = b->h[i];
+                ivf_stats* s = stats + (size_t)r * count + i;
+                ivf_status st = assign_stats(h, s, false);
+                if (st != IVF_OK) return bfail(b, st, h->err);
+                double ds[2];
+                Counters c;
+                BHIP(b, hipMemcpy(ds, h->dscal, sizeof(ds), hipMemcpyDeviceToHost));
+                BHIP(b, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
+                int64_t nnz_now = 0;
+                BHIP(b, hipMemcpy(&nnz_now, h->mm_ptr[h->cur] + h->k, sizeof(int64_t),
+                                  hipMemcpyDeviceToHost));
+                s->objective_exact = ds[1];
+                s->empty_clusters = (int64_t)c.empty;
+                s->nnz_means = nnz_now;
+                s->assign_ms = ms;   // the whole iteration of the batch
+                s->update_ms = 0.f;
+            }
+        }
+    }
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return IVF_OK;
+}
+
+ivf_status ivf_batch_get_means(ivf_batch* b, int32_t inst, ivf_means* out) {
+    if (!b || inst < 0 || inst >= (int32_t)b->h.size()) return bfail(b, IVF_ERR_ARG, "bad instance");
+    ivf_status st = ivf_get_means(b->h[inst], out);
+    if (st != IVF_OK) return bfail(b, st, b->h[inst]->err);
+    return IVF_OK;
+}
+
+ivf_status ivf_batch_set_slack(ivf_batch* b, double frac, int64_t abs_entries) {
+    if (!b || !(frac >= 0.0) || frac > 64.0 || abs_entries < 0)
+        return bfail(b, IVF_ERR_ARG, "slack must be 0 <= frac <= 64, abs >= 0");
+    b->slack_frac = frac;
+    b->slack_abs = abs_entries;
+    if (b->eager_left == 0) return batch_fix_capacities(b);   // grows only
+    return IVF_OK;
+}
+
+ivf_status ivf_batch_get_plan(const ivf_batch* b, int32_t plan[8]) {
+    if (!b || !plan) return IVF_ERR_ARG;
+    plan[0] = b->kr_max;
+    plan[1] = b->waves;
+    plan[2] = b->tile_stride;
+    plan[3] = b->grid;
+    plan[4] = (b->exec[0] && b->exec[1]) ? 1 : 0;
+    plan[5] = b->tuned ? 1 : 0;
+    plan[6] = b->captures;
+    plan[7] = b->recoveries;
+    return IVF_OK;
+}
+
+void ivf_batch_destroy(ivf_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (ivf_handle* h : b->h) {
+        free_handle(h);
+        delete h;
+    }
+    for (ObjView* v : b->views) {
+        v->release();
+        delete v;
+    }
+    if (b->sc) { b->sc->release(); delete b->sc; }
+    dfree(b->d_args);
+    dfree(b->d_item_off);
+    dfree(b->d_flags);
+    dfree(b->d_cnt);
+    for (auto& e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char* ivf_batch_last_error(const ivf_batch* b) {
+    return b ? b->err.c_str() : g_build_error.c_str();
 }
 
 }  // extern "C"

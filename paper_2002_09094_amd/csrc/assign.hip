@@ -169,142 +169,178 @@ __device__ inline void top2_combine(float& b, int32_t& id, float& s, float ob, i
     }
 }
 
+// One work item: `chunk` consecutive objects against cluster range r, each
+// walked into the wave's tile, its range record written and the tile cleared.
+template <int VT>
+__device__ inline void walk_item(const WalkArgs& a, int64_t w, float* tile, int lane) {
+    const int r = (int)(w / a.items_per_range);
+    const int64_t c = w - (int64_t)r * a.items_per_range;
+    const int32_t base = r * a.k_r;
+    const int32_t kr = min(a.k_r, a.k - base);
+    const int64_t i0 = c * a.chunk;
+    const int64_t i1 = min(a.n, i0 + a.chunk);
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
+        int32_t m = 0;
+        for (int64_t h0 = hb; h0 < he; h0 += kWave) {
+            const int cnt = (int)min((int64_t)kWave, he - h0);
+            float v = 0.f;
+            int64_t pos = 0, count = 0;
+            if (lane < cnt) {
+                const int32_t t = a.x_idx[h0 + lane];
+                v = a.x_val[h0 + lane];
+                const SliceDesc ds = a.desc[(int64_t)t * a.R + r];
+                pos = ds.pos;
+                count = ds.count;
+            }
+            for (int hh = 0; hh < cnt; ++hh) {
+                const int64_t p = rl64(pos, hh), cn = rl64(count, hh);
+                const float vv = rlf(v, hh);
+                m += (int32_t)cn;
+                if (p >= 0)
+                    walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p,
+                                   p + cn, vv, tile, base, lane);
+                else
+                    walk_dense<VT>(reinterpret_cast<const typename Slab<VT>::T*>(
+                                       reinterpret_cast<const char*>(a.slab) +
+                                       (-p - 1) * (VT == IVF_VAL_F32 ? 4 : 2)),
+                                   (kr + 3) >> 2, vv, tile, lane);
+            }
+        }
+        // fused top-2 over the tile, clearing it for the next object
+        float b = 0.f, s2 = 0.f;
+        int32_t id = -1;
+        for (int s0 = lane * 4; s0 < kr; s0 += 4 * kWave) {
+            const float4 q = *reinterpret_cast<const float4*>(tile + s0);
+            *reinterpret_cast<float4*>(tile + s0) = make_float4(0.f, 0.f, 0.f, 0.f);
+            const float x[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (x[u] > b) {
+                    s2 = fmaxf(s2, b);
+                    b = x[u];
+                    id = s0 + u;
+                } else {
+                    s2 = fmaxf(s2, x[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) {
+            const float ob = __shfl_xor(b, o, kWave);
+            const int32_t oid = __shfl_xor(id, o, kWave);
+            const float os = __shfl_xor(s2, o, kWave);
+            top2_combine(b, id, s2, ob, oid, os);
+        }
+        // every lane holds the same record: identical stores, no divergence
+        RangeRec rec;
+        rec.best = b;
+        rec.id = id >= 0 ? base + id : -1;
+        rec.second = s2;
+        rec.m = m;
+        a.rec[i * a.R + r] = rec;
+    }
+}
+
+__device__ inline void zero_tile(float* tile, int stride, int lane) {
+    for (int s = lane * 4; s < stride; s += 4 * kWave)
+        *reinterpret_cast<float4*>(tile + s) = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 template <int VT>
 __global__ __launch_bounds__(kWave * kMaxWaves) void k_walk(WalkArgs a) {
     extern __shared__ float4 lds4[];
-    float* lds = reinterpret_cast<float*>(lds4);
     const int lane = lane_id();
     // wave index made provably uniform, so every loop below has uniform bounds
     // and cross-lane reads always see all 64 lanes active
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    float* tile = lds + (int64_t)wv * a.tile_stride;
-    for (int s = lane * 4; s < a.tile_stride; s += 4 * kWave)
-        *reinterpret_cast<float4*>(tile + s) = make_float4(0.f, 0.f, 0.f, 0.f);
+    float* tile = reinterpret_cast<float*>(lds4) + (int64_t)wv * a.tile_stride;
+    zero_tile(tile, a.tile_stride, lane);
     const int64_t total = a.items_per_range * a.R;
-    unsigned long long m_acc = 0;
     // items in ascending order, round robin over the waves: all waves sweep
-    // the ranges in the same order, so a range's posting slices stay hot
-    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves) {
-        const int r = (int)(w / a.items_per_range);
-        const int64_t c = w - (int64_t)r * a.items_per_range;
-        const int32_t base = r * a.k_r;
-        const int32_t kr = min(a.k_r, a.k - base);
-        const int64_t i0 = c * a.chunk;
-        const int64_t i1 = min(a.n, i0 + a.chunk);
-        for (int64_t i = i0; i < i1; ++i) {
-            const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
-            int32_t m = 0;
-            for (int64_t h0 = hb; h0 < he; h0 += kWave) {
-                const int cnt = (int)min((int64_t)kWave, he - h0);
-                float v = 0.f;
-                int64_t pos = 0, count = 0;
-                if (lane < cnt) {
-                    const int32_t t = a.x_idx[h0 + lane];
-                    v = a.x_val[h0 + lane];
-                    const SliceDesc ds = a.desc[(int64_t)t * a.R + r];
-                    pos = ds.pos;
-                    count = ds.count;
-                }
-                for (int hh = 0; hh < cnt; ++hh) {
-                    const int64_t p = rl64(pos, hh), c = rl64(count, hh);
-                    const float vv = rlf(v, hh);
-                    m += (int32_t)c;
-                    if (p >= 0)
-                        walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p,
-                                       p + c, vv, tile, base, lane);
-                    else
-                        walk_dense<VT>(reinterpret_cast<const typename Slab<VT>::T*>(
-                                           reinterpret_cast<const char*>(a.slab) +
-                                           (-p - 1) * (VT == IVF_VAL_F32 ? 4 : 2)),
-                                       (kr + 3) >> 2, vv, tile, lane);
-                }
-            }
-            // fused top-2 over the tile, clearing it for the next object
-            float b = 0.f, s2 = 0.f;
-            int32_t id = -1;
-            for (int s0 = lane * 4; s0 < kr; s0 += 4 * kWave) {
-                const float4 q = *reinterpret_cast<const float4*>(tile + s0);
-                *reinterpret_cast<float4*>(tile + s0) = make_float4(0.f, 0.f, 0.f, 0.f);
-                const float x[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (x[u] > b) {
-                        s2 = fmaxf(s2, b);
-                        b = x[u];
-                        id = s0 + u;
-                    } else {
-                        s2 = fmaxf(s2, x[u]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int o = kWave / 2; o >= 1; o >>= 1) {
-                const float ob = __shfl_xor(b, o, kWave);
-                const int32_t oid = __shfl_xor(id, o, kWave);
-                const float os = __shfl_xor(s2, o, kWave);
-                top2_combine(b, id, s2, ob, oid, os);
-            }
-            // every lane holds the same record: identical stores, no divergence
-            RangeRec rec;
-            rec.best = b;
-            rec.id = id >= 0 ? base + id : -1;
-            rec.second = s2;
-            rec.m = m;
-            a.rec[i * a.R + r] = rec;
-            m_acc += (unsigned long long)m;
-        }
-    }
-    atomicAdd(&a.cnt->mult, lane == 0 ? m_acc : 0ull);
+    // the ranges in the same order, so a range's slices stay hot in the caches
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves)
+        walk_item<VT>(a, w, tile, lane);
 }
 
-__global__ void k_merge(MergeArgs a) {
+// Many instances in one persistent launch: item w belongs to the instance b
+// with item_off[b] <= w < item_off[b + 1]; every wave's tile holds the widest
+// range of all instances.
+template <int VT>
+__global__ __launch_bounds__(kWave * kMaxWaves) void k_walk_batch(const WalkArgs* __restrict__ args,
+                                                                  const int64_t* __restrict__ item_off,
+                                                                  int32_t count, int32_t tile_stride) {
+    extern __shared__ float4 lds4[];
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    float* tile = reinterpret_cast<float*>(lds4) + (int64_t)wv * tile_stride;
+    zero_tile(tile, tile_stride, lane);
+    const int64_t total = item_off[count];
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves) {
+        int32_t lo = 0, hi = count;   // last b with item_off[b] <= w
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (item_off[mid] <= w) lo = mid; else hi = mid;
+        }
+        const WalkArgs a = args[lo];
+        walk_item<VT>(a, w - item_off[lo], tile, lane);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
-    float b = 0.f, s2 = 0.f;
-    int32_t id = -1;
     int64_t m = 0;
-    for (int r = 0; r < a.R; ++r) {
-        const RangeRec rec = a.rec[i * a.R + r];
-        m += rec.m;
-        // ranges arrive in ascending cluster order: an equal best keeps the earlier
-        if (rec.best > b) {
-            s2 = fmaxf(fmaxf(s2, b), rec.second);
-            b = rec.best;
-            id = rec.id;
-        } else {
-            s2 = fmaxf(s2, rec.best);
+    if (i < a.n) {
+        float b = 0.f, s2 = 0.f;
+        int32_t id = -1;
+        for (int r = 0; r < a.R; ++r) {
+            const RangeRec rec = a.rec[i * a.R + r];
+            m += rec.m;
+            // ranges arrive in ascending cluster order: an equal best keeps the earlier
+            if (rec.best > b) {
+                s2 = fmaxf(fmaxf(s2, b), rec.second);
+                b = rec.best;
+                id = rec.id;
+            } else {
+                s2 = fmaxf(s2, rec.best);
+            }
         }
-    }
-    const int32_t prev = a.prev[i];
-    a.best[i] = b;
-    a.best_id[i] = id;
-    a.second[i] = s2;
-    uint8_t flag;
-    if (m == 0) {                      // no term shared with any mean
-        a.assign[i] = prev;
-        a.rho[i] = 0.0;
-        flag = 4;
-        atomicAdd(&a.cnt->zero_overlap, 1ull);
-    } else {
-        double c, ab, g;
-        cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], &c, &ab, &g);
-        const bool ok = !a.force_rescore && b > 0.f &&
-                        cert_lb((double)b, c, ab, g) > cert_ub((double)s2, c, ab, g);
-        if (ok || !a.certify) {
-            a.assign[i] = id >= 0 ? id : prev;
-            a.rho[i] = (double)b;
-            flag = ok ? 1 : 0;
-            if (ok) atomicAdd(&a.cnt->certified, 1ull);
-            const double rel = c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0);
-            atomicMax(&a.cnt->max_bound_bits, (unsigned long long)__double_as_longlong(rel));
+        const int32_t prev = a.prev[i];
+        a.best[i] = b;
+        a.best_id[i] = id;
+        a.second[i] = s2;
+        uint8_t flag;
+        if (m == 0) {                      // no term shared with any mean
+            a.assign[i] = prev;
+            a.rho[i] = 0.0;
+            flag = 4;
+            atomicAdd(&a.cnt->zero_overlap, 1ull);
         } else {
-            const unsigned long long slot = atomicAdd(&a.cnt->n_rescore, 1ull);
-            a.rescore_list[slot] = (int32_t)i;
-            flag = 2;
+            double c, ab, g;
+            cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], &c, &ab, &g);
+            const bool ok = !a.force_rescore && b > 0.f &&
+                            cert_lb((double)b, c, ab, g) > cert_ub((double)s2, c, ab, g);
+            if (ok || !a.certify) {
+                a.assign[i] = id >= 0 ? id : prev;
+                a.rho[i] = (double)b;
+                flag = ok ? 1 : 0;
+                if (ok) atomicAdd(&a.cnt->certified, 1ull);
+                const double rel = c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0);
+                atomicMax(&a.cnt->max_bound_bits, (unsigned long long)__double_as_longlong(rel));
+            } else {
+                const unsigned long long slot = atomicAdd(&a.cnt->n_rescore, 1ull);
+                a.rescore_list[slot] = (int32_t)i;
+                flag = 2;
+            }
         }
+        a.flags[i] = flag;
     }
-    a.flags[i] = flag;
+    // the entries walked (M), summed per wave: one atomic per wave
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o, kWave);
+    if (lane_id() == 0 && m) atomicAdd(&a.cnt->mult, (unsigned long long)m);
 }
 
 // One wave per queued object; an FP64 score tile of k_r64 clusters in LDS.
@@ -453,22 +489,44 @@ hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes,
     return hipGetLastError();
 }
 
+hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int32_t count,
+                             int32_t tile_stride, int valtype, int waves, int grid,
+                             hipStream_t s) {
+    const dim3 blk(kWave * waves);
+    const size_t lds = (size_t)waves * tile_stride * 4;
+    if (valtype == IVF_VAL_F32)
+        k_walk_batch<IVF_VAL_F32><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride);
+    else if (valtype == IVF_VAL_BF16)
+        k_walk_batch<IVF_VAL_BF16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride);
+    else
+        k_walk_batch<IVF_VAL_F16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride);
+    return hipGetLastError();
+}
+
 const void* walk_kernel_ptr(int valtype) {
     if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32>);
     if (valtype == IVF_VAL_BF16) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_BF16>);
     return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F16>);
 }
 
+const void* walk_batch_kernel_ptr(int valtype) {
+    if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F32>);
+    if (valtype == IVF_VAL_BF16) return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_BF16>);
+    return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F16>);
+}
+
 hipError_t walk_set_lds_limit(int lds_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_walk<IVF_VAL_BF16>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_walk<IVF_VAL_F16>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    if (e != hipSuccess) return e;
+    // the attribute is per kernel and shared by every handle: allow the whole
+    // LDS, each launch asks for what its tiles need
+    lds_bytes = kLdsBytes;
+    const void* ks[] = {walk_kernel_ptr(IVF_VAL_F32), walk_kernel_ptr(IVF_VAL_BF16),
+                        walk_kernel_ptr(IVF_VAL_F16), walk_batch_kernel_ptr(IVF_VAL_F32),
+                        walk_batch_kernel_ptr(IVF_VAL_BF16), walk_batch_kernel_ptr(IVF_VAL_F16)};
+    for (const void* k : ks) {
+        hipError_t e =
+            hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore),
                                hipFuncAttributeMaxDynamicSharedMemorySize, 8 * 8192);
 }

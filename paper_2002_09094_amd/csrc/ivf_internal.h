@@ -67,7 +67,16 @@ enum : unsigned {
     kBadOrder = 4u,
     kNonFinite = 8u,
     kNonPositive = 16u,
+    kOverflow = 32u,   // new means exceeded a fixed capacity
 };
+
+// Entry count of a capacity-bounded launch: the device-side count when it
+// fits the capacity n, else 0 (a producer that overflowed wrote nothing valid).
+__device__ inline int64_t bounded_count(int64_t n, const int64_t* n_dev) {
+    if (!n_dev) return n;
+    const int64_t v = *n_dev;
+    return (v >= 0 && v <= n) ? v : 0;
+}
 
 // Certification constants: see ivf_cert_bound in ivf.h.
 __host__ __device__ inline void cert_consts(int valtype, int64_t nt, double* c, double* a,
@@ -107,11 +116,13 @@ hipError_t exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* 
 // Buffers: keys/vals are in-out (result lands back in keys/vals);
 // keys_alt/vals_alt are scratch of n entries; tmp holds radix_tmp_bytes(n).
 // If vals_in_first != nullptr, the first pass reads values from it instead
-// of vals (saves a copy of an immutable payload).
+// of vals (saves a copy of an immutable payload).  If n_dev != nullptr, the
+// number of pairs is min(n, *n_dev), read on the device (n is the capacity).
 size_t radix_tmp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                             uint32_t* vals_alt, int64_t n, int bits, void* tmp, hipStream_t s,
-                            const uint32_t* vals_in_first = nullptr);
+                            const uint32_t* vals_in_first = nullptr,
+                            const int64_t* n_dev = nullptr);
 
 // Plan of the walk for k clusters.
 ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err);

@@ -56,6 +56,11 @@ struct RescoreArgs {
 hipError_t launch_clear_counters(Counters* c, hipStream_t s);
 hipError_t walk_set_lds_limit(int lds_bytes);
 const void* walk_kernel_ptr(int valtype);
+const void* walk_batch_kernel_ptr(int valtype);
+// Walk of many instances in one persistent launch (args, item_off: device).
+hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int32_t count,
+                             int32_t tile_stride, int valtype, int waves, int grid,
+                             hipStream_t s);
 hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes, int grid,
                        hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
@@ -124,6 +129,7 @@ struct UpdateArgs {
     const int32_t* old_idx;
     const double* old_val;
     int64_t* new_ptr;
+    int64_t new_cap;    // entries the new-means buffers hold
     int32_t* new_idx;
     double* new_val;
     int32_t* new_row;
@@ -142,7 +148,8 @@ hipError_t launch_objective_exact(const double* objpart, int32_t k, double* out,
 hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStream_t s);
 
 struct IvfArgs {
-    int64_t d, nnzM;
+    int64_t d, nnzM;          // nnzM: entries, or their capacity if nnz_dev is set
+    const int64_t* nnz_dev;   // device-side entry count (nullable)
     int32_t k, k_r, R, valtype;
     float dense_threshold;
     const int32_t* mm_idx;
@@ -167,9 +174,9 @@ struct IvfArgs {
 // lists in ascending cluster order with the stored-precision values, slice
 // descriptors and the scanned dense-slab offsets (total at dsz[d * R]).
 hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s);
-// Phase 2 (after the slab array is sized): dense slabs filled, descriptors
-// of dense slices pointed at them.
-hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_elems, hipStream_t s);
+// Phase 2: dense slabs filled (the array holds slab_cap elements; slices that
+// do not fit stay sparse), descriptors of dense slices pointed at them.
+hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_cap, hipStream_t s);
 hipError_t launch_seed_assign(const int32_t* seeds, int32_t k, int64_t n, int32_t* assign,
                               hipStream_t s);
 

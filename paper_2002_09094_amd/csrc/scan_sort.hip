@@ -2,6 +2,8 @@
 // value) pairs for gfx950.  Both are building blocks of the update step
 // (grouping object entries by cluster) and of the inverted-file transpose
 // (grouping mean entries by term), which need stable, deterministic orders.
+#include <algorithm>
+
 #include "ivf_internal.h"
 
 namespace ivf {
@@ -115,10 +117,11 @@ hipError_t scan_impl(const T* in, T* out, int64_t n, void* tmp, hipStream_t s) {
 
 // ------------------------------------------------------------- radix sort
 __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                       int64_t n, int shift,
+                                                       int64_t n, const int64_t* n_dev, int shift,
                                                        uint32_t* __restrict__ hist,
                                                        int64_t nt) {
     __shared__ uint32_t h[kDigits];
+    n = bounded_count(n, n_dev);
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
@@ -133,10 +136,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
 
 // Stable scatter: items are ranked in their input order (round, wave, lane).
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n, int shift,
-    const uint32_t* __restrict__ offs, int64_t nt, uint32_t* __restrict__ okeys,
-    uint32_t* __restrict__ ovals) {
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n,
+    const int64_t* n_dev, int shift, const uint32_t* __restrict__ offs, int64_t nt,
+    uint32_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
     constexpr int W = kBlock / kWave;
+    n = bounded_count(n, n_dev);
     __shared__ uint32_t run[kDigits];
     __shared__ uint32_t wcnt[W][kDigits];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
@@ -182,6 +186,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     }
 }
 
+// The result of an odd number of passes copied back (a kernel, so the sort
+// records no memory-copy node of host-chosen size when captured in a graph).
+__global__ void k_copy2(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
+                        uint32_t* __restrict__ oa, uint32_t* __restrict__ ob, int64_t n,
+                        const int64_t* n_dev) {
+    n = bounded_count(n, n_dev);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        oa[i] = a[i];
+        ob[i] = b[i];
+    }
+}
+
 }  // namespace
 
 size_t scan_tmp_bytes(int64_t n) { return scan_levels_bytes<int64_t>(n) + 256; }
@@ -204,7 +221,7 @@ size_t radix_tmp_bytes(int64_t n) {
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                             uint32_t* vals_alt, int64_t n, int bits, void* tmp, hipStream_t s,
-                            const uint32_t* vals_in_first) {
+                            const uint32_t* vals_in_first, const int64_t* n_dev) {
     if (n <= 0) return hipSuccess;
     if (bits < 1) bits = 1;
     const int64_t nt = ntiles(n);
@@ -216,20 +233,19 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         const uint32_t* vin = (p == 0 && vals_in_first) ? vals_in_first : vi;
-        k_radix_hist<<<(unsigned)nt, kBlock, 0, s>>>(ki, n, shift, hist, nt);
+        k_radix_hist<<<(unsigned)nt, kBlock, 0, s>>>(ki, n, n_dev, shift, hist, nt);
         hipError_t e = scan_impl<uint32_t>(hist, hist, nt * kDigits, stmp, s);
         if (e != hipSuccess) return e;
-        k_radix_scatter<<<(unsigned)nt, kBlock, 0, s>>>(ki, vin, n, shift, hist, nt, ko, vo);
+        k_radix_scatter<<<(unsigned)nt, kBlock, 0, s>>>(ki, vin, n, n_dev, shift, hist, nt, ko, vo);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         uint32_t* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
     if (ki != keys) {   // odd number of passes: move the result home
-        hipError_t e = hipMemcpyAsync(keys, ki, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(vals, vi, (size_t)n * 4, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
+        k_copy2<<<(unsigned)std::min<int64_t>(nt * kItems, 65536), kBlock, 0, s>>>(
+            ki, vi, keys, vals, n, n_dev);
+        return hipGetLastError();
     }
     return hipSuccess;
 }

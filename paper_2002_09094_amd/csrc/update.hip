@@ -90,7 +90,9 @@ __global__ void k_iota(uint32_t* out, int64_t n) {
         out[i] = (uint32_t)i;
 }
 
-__global__ void k_copy_keys(const int32_t* in, uint32_t* out, int64_t n) {
+__global__ void k_copy_keys(const int32_t* in, uint32_t* out, int64_t n,
+                            const int64_t* n_dev = nullptr) {
+    n = bounded_count(n, n_dev);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         out[i] = (uint32_t)in[i];
@@ -314,6 +316,10 @@ __global__ __launch_bounds__(kThreads) void k_fill(UpdateArgs a) {
     if (j >= a.k) return;
     const int64_t nj = a.size[j];
     const int64_t p0 = a.new_ptr[j];
+    if (a.new_ptr[a.k] > a.new_cap) {   // the new means do not fit: flag, write nothing
+        if (j == 0 && lane == 0) atomicOr(&a.cnt->error_flags, (unsigned long long)kOverflow);
+        return;
+    }
     if (nj == 0) {
         const int64_t ob = a.old_ptr[j], oe = a.old_ptr[j + 1];
         for (int64_t e = ob + lane; e < oe; e += kWave) {
@@ -359,9 +365,10 @@ __device__ inline uint32_t bf16_rne(float f) {
 }
 
 __global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __restrict__ mm_row,
-                           const double* __restrict__ mm_val, int64_t nnzM, int32_t k_r,
-                           int valtype, int32_t* __restrict__ cid, double* __restrict__ val64,
-                           void* __restrict__ post) {
+                           const double* __restrict__ mm_val, int64_t nnzM, const int64_t* n_dev,
+                           int32_t k_r, int valtype, int32_t* __restrict__ cid,
+                           double* __restrict__ val64, void* __restrict__ post) {
+    nnzM = bounded_count(nnzM, n_dev);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
          q += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t p = vals[q];
@@ -382,9 +389,11 @@ __global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __r
     }
 }
 
-__global__ void k_ivf_ptr(const uint32_t* skeys, int64_t nnzM, int64_t d, int64_t* ptr) {
+__global__ void k_ivf_ptr(const uint32_t* skeys, int64_t nnzM, const int64_t* n_dev, int64_t d,
+                          int64_t* ptr) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > d) return;
+    nnzM = bounded_count(nnzM, n_dev);
     int64_t lo = 0, hi = nnzM;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
@@ -417,17 +426,18 @@ __global__ void k_desc(const int64_t* ptr, const int32_t* cid, int64_t d, int32_
     }
 }
 
-__global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, const int64_t* dsz_next,
-                             int64_t nslices) {
-    // a slice is dense iff its scanned offset grows: doff[s + 1] > doff[s]
+__global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, int64_t nslices,
+                             int64_t cap) {
+    // a slice is dense iff its scanned offset grows: doff[s + 1] > doff[s];
+    // one that would not fit the slab capacity stays sparse (same scores)
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslices;
          s += (int64_t)gridDim.x * blockDim.x)
-        if (doff[s + 1] > doff[s]) desc[s].pos = -(doff[s] + 1);
-    (void)dsz_next;
+        if (doff[s + 1] > doff[s] && doff[s + 1] <= cap) desc[s].pos = -(doff[s] + 1);
 }
 
 template <typename T>
-__global__ void k_zero_t(T* p, int64_t n) {
+__global__ void k_zero_t(T* p, int64_t n, const int64_t* n_dev = nullptr) {
+    if (n_dev) n = min(n, *n_dev);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = (T)0;
@@ -436,12 +446,14 @@ __global__ void k_zero_t(T* p, int64_t n) {
 // Dense slabs take every entry of their slice at its cluster's offset.
 __global__ void k_slab_scatter(const uint32_t* __restrict__ skeys, const int32_t* __restrict__ cid,
                                const void* __restrict__ post, const SliceDesc* __restrict__ desc,
-                               int64_t nnzM, int32_t R, int32_t k_r, int valtype,
-                               void* __restrict__ slab) {
+                               int64_t nnzM, const int64_t* n_dev, int64_t d, int32_t k,
+                               int32_t R, int32_t k_r, int valtype, void* __restrict__ slab) {
+    nnzM = bounded_count(nnzM, n_dev);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
          q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = skeys[q];
         const int32_t j = cid[q];
+        if (t >= d || j < 0 || j >= k) continue;   // never true for validated means
         const int32_t r = j / k_r;
         const int64_t pos = desc[t * R + r].pos;
         if (pos >= 0) continue;
@@ -579,34 +591,41 @@ hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStre
 }
 
 hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
+    // a.nnzM: the entry count, or the capacity when a.nnz_dev holds the count
     if (a.nnzM > 0) {
-        k_copy_keys<<<capped(a.nnzM), kThreads, 0, s>>>(a.mm_idx, a.keys, a.nnzM);
+        k_copy_keys<<<capped(a.nnzM), kThreads, 0, s>>>(a.mm_idx, a.keys, a.nnzM, a.nnz_dev);
         HIP_RET(hipGetLastError());
         HIP_RET(radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.nnzM,
-                                 bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, a.iota));
-        k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM, a.k_r,
-                                                       a.valtype, a.cid, a.val64, a.post);
+                                 bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, a.iota,
+                                 a.nnz_dev));
+        k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM,
+                                                       a.nnz_dev, a.k_r, a.valtype, a.cid,
+                                                       a.val64, a.post);
         HIP_RET(hipGetLastError());
     }
-    k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.d, a.ivf_ptr);
+    k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.nnz_dev, a.d, a.ivf_ptr);
     k_desc<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.ivf_ptr, a.cid, a.d, a.k, a.R, a.k_r,
                                                   a.dense_threshold, a.desc, a.dsz);
     HIP_RET(hipGetLastError());
     return exclusive_scan_i64(a.dsz, a.dsz, a.d * a.R + 1, a.tmp, s);
 }
 
-hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_elems, hipStream_t s) {
+hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_cap, hipStream_t s) {
+    // slab_cap: elements the slab array holds; the needed total is at dsz[d * R]
     const int64_t ns = a.d * a.R;
-    if (slab_elems <= 0) return hipSuccess;
-    k_desc_dense<<<capped(ns), kThreads, 0, s>>>(a.desc, a.dsz, nullptr, ns);
+    if (slab_cap <= 0) return hipSuccess;
+    k_desc_dense<<<capped(ns), kThreads, 0, s>>>(a.desc, a.dsz, ns, slab_cap);
+    const int64_t* total = a.dsz + ns;
     if (a.valtype == IVF_VAL_F32)
-        k_zero_t<float><<<capped(slab_elems), kThreads, 0, s>>>(
-            reinterpret_cast<float*>(a.slab), slab_elems);
+        k_zero_t<float><<<capped(slab_cap), kThreads, 0, s>>>(reinterpret_cast<float*>(a.slab),
+                                                               slab_cap, total);
     else
-        k_zero_t<uint16_t><<<capped(slab_elems), kThreads, 0, s>>>(
-            reinterpret_cast<uint16_t*>(a.slab), slab_elems);
-    k_slab_scatter<<<capped(a.nnzM), kThreads, 0, s>>>(a.keys, a.cid, a.post, a.desc, a.nnzM, a.R,
-                                                       a.k_r, a.valtype, a.slab);
+        k_zero_t<uint16_t><<<capped(slab_cap), kThreads, 0, s>>>(
+            reinterpret_cast<uint16_t*>(a.slab), slab_cap, total);
+    if (a.nnzM > 0)
+        k_slab_scatter<<<capped(a.nnzM), kThreads, 0, s>>>(a.keys, a.cid, a.post, a.desc, a.nnzM,
+                                                           a.nnz_dev, a.d, a.k, a.R, a.k_r,
+                                                           a.valtype, a.slab);
     return hipGetLastError();
 }
 

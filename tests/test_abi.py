@@ -127,3 +127,20 @@ def test_cert_bound_holds_for_emulated_fp32_scores(vt):
         c, a, _ = ivf.cert_bound(vt, nt)
         err = abs(Fraction(float(acc)) - exact)
         assert err <= Fraction(c) * exact + Fraction(a), (vt, trial, float(err), float(exact))
+
+
+def test_batch_build_rejects_bad_arguments_before_any_launch():
+    lib = _lib.get()
+    b = ctypes.c_void_p()
+    xs = (_lib.ivf_csr * 2)(_lib.ivf_csr(10, 5, 20, 1, 1, 1), _lib.ivf_csr(8, 5, 20, 1, 1, 1))
+    ks = (ctypes.c_int32 * 2)(3, 9)                      # k > n in the second instance
+    assert lib.ivf_batch_build(2, xs, ks, None, ctypes.byref(b)) == -1
+    assert b"k outside" in lib.ivf_batch_last_error(None)
+    assert lib.ivf_batch_build(0, xs, ks, None, ctypes.byref(b)) == -1
+    assert lib.ivf_batch_build(2, None, ks, None, ctypes.byref(b)) == -1
+    big = (_lib.ivf_csr * 1)(_lib.ivf_csr(10, 5, 1 << 31, 1, 1, 1))
+    k1 = (ctypes.c_int32 * 1)(3)
+    assert lib.ivf_batch_build(1, big, k1, None, ctypes.byref(b)) == -5
+    assert b.value is None
+    assert lib.ivf_batch_set_slack(None, 0.5, 0) == -1
+    lib.ivf_batch_destroy(None)                           # no-op

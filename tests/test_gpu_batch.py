@@ -1,0 +1,147 @@
+"""GPU parity of the batched form: many instances of uneven N, D and k (and
+restarts of one object set) advanced together, one persistent walk launch per
+iteration, the iteration replayed from recorded HIP graphs.
+
+Every instance must compute exactly what one handle of the same options
+computes: identical assignments at every iteration and bit-identical means.
+Between replays the test does its own eager work (single-handle iterations,
+copies to the host, synchronisations), and every replay is checked.  Two
+instances are also checked against the FP64 oracle's chain directly.
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2002_09094_amd as ivf  # noqa: E402
+from gpu_util import i32, means_to_host, to_dev  # noqa: E402
+
+# (n, d, lam, lo, hi, s, k, seed, restarts)
+SETS = [
+    (3000, 2000, 20.0, 1, 80, 1.1, 40, 101, 1),
+    (1237, 997, 12.0, 0, 50, 1.2, 37, 105, 1),
+    (9000, 6000, 35.0, 3, 300, 1.05, 700, 301, 1),
+    (500, 400, 10.0, 1, 40, 1.1, 1, 103, 1),
+    (6000, 3000, 60.0, 5, 400, 1.15, 1500, 302, 1),
+    (2500, 1500, 30.0, 2, 100, 1.1, 120, 201, 4),   # one object set, four restarts
+]
+
+
+def _instances():
+    out = []
+    for (n, d, lam, lo, hi, s, k, seed, reps) in SETS:
+        x = datagen.generate(n, d, lam, lo, hi, s, seed)
+        dx = to_dev(x)
+        for r in range(reps):
+            out.append((x, dx, d, k, datagen.seed_objects(x, k, seed + 1000 * r)))
+    return out
+
+
+def _run_against_singles(inst, iters, batch_opts, single_opts, slack=None):
+    b = ivf.IVFBatch([(dx[0], dx[1], dx[2], d) for (_, dx, d, _, _) in inst],
+                     [k for (_, _, _, k, _) in inst], **batch_opts)
+    if slack is not None:
+        b.set_slack(*slack)
+    singles = []
+    for (x, dx, d, k, seeds) in inst:
+        km = ivf.IVFKMeans(*dx, d, k, **single_opts)
+        km.init_seeds(i32(seeds))
+        singles.append(km)
+    b.init_seeds([i32(sd) for (_, _, _, _, sd) in inst])
+    ba = [i32(np.full(x.n, -1, np.int32)) for (x, _, _, _, _) in inst]
+    sa = [i32(np.full(x.n, -1, np.int32)) for (x, _, _, _, _) in inst]
+    plans = []
+    for r in range(iters):
+        bst = b.iterate(1, ba)[0]
+        plans.append(b.plan)
+        for i, km in enumerate(singles):
+            s1 = km.assign(sa[i])
+            s2 = km.update(sa[i])
+            ga, gs = ba[i].cpu().numpy(), sa[i].cpu().numpy()
+            mism = np.nonzero(ga != gs)[0]
+            assert len(mism) == 0, ("iteration", r, "instance", i, mism[:10])
+            for key in ("changed", "mult_adds", "certified", "rescored", "zero_overlap"):
+                assert bst[i][key] == s1[key], (r, i, key, bst[i][key], s1[key])
+            assert bst[i]["objective"] == s1["objective"]
+            assert bst[i]["objective_exact"] == s2["objective_exact"]
+            assert bst[i]["empty_clusters"] == s2["empty_clusters"]
+            assert bst[i]["nnz_means"] == s2["nnz_means"]
+        torch.cuda.synchronize()
+    for i, km in enumerate(singles):
+        bp, bi, bv = (t.cpu().numpy() for t in b.get_means(i))
+        sp, si, sv = (t.cpu().numpy() for t in km.get_means())
+        assert np.array_equal(bp, sp) and np.array_equal(bi, si)
+        assert np.array_equal(bv, sv)           # bit-identical FP64 means
+        km.close()
+    plan = b.plan
+    b.close()
+    return plans, plan
+
+
+def test_batch_equals_single_handles_with_autotuned_tiles():
+    inst = _instances()
+    print("instances", len(inst), flush=True)
+    plans, plan = _run_against_singles(inst, 7, {}, {})
+    print("plan", plan, flush=True)
+    assert plans[0]["graphs"] == 0 and plans[1]["tuned"] == 1
+    assert plans[2]["graphs"] == 1 and plan["captures"] >= 1
+    assert plan["kr_max"] in (640, 1280, 2560)
+
+
+def test_batch_overflow_recovery_and_fixed_tiles():
+    # no slack: the first replays outgrow the fixed buffers; every overflow is
+    # redone eagerly and the graphs recorded again, with identical results
+    inst = _instances()
+    opts = {"cluster_range": 64, "waves_per_wg": 3}
+    plans, plan = _run_against_singles(inst, 7, opts, opts, slack=(0.0, 0))
+    print("plan", plan, flush=True)
+    assert plan["tuned"] == 0 and plan["kr_max"] == 64 and plan["waves"] == 3
+    assert plan["recoveries"] >= 1 and plan["captures"] >= 2
+
+
+@pytest.mark.parametrize("valtype", ["bf16", "f16"])
+def test_batch_low_precision_values(valtype):
+    inst = _instances()[:5]
+    _run_against_singles(inst, 4, {"valtype": valtype}, {"valtype": valtype})
+
+
+def test_batch_chain_against_oracle():
+    inst = [v for v in _instances() if v[3] in (40, 37)]
+    b = ivf.IVFBatch([(dx[0], dx[1], dx[2], d) for (_, dx, d, _, _) in inst],
+                     [k for (_, _, _, k, _) in inst])
+    b.init_seeds([i32(sd) for (_, _, _, _, sd) in inst])
+    ba = [i32(np.full(x.n, -1, np.int32)) for (x, _, _, _, _) in inst]
+    chains = [oracle.chain(x, seeds, 6) for (x, _, _, _, seeds) in inst]
+    for r in range(6):
+        bst = b.iterate(1, ba)[0]
+        for i, ch in enumerate(chains):
+            st = next(ch)
+            assert np.array_equal(ba[i].cpu().numpy(), st.assign.assign), (r, i)
+            assert bst[i]["mult_adds"] == st.assign.mult_adds
+            assert bst[i]["objective"] == pytest.approx(st.assign.objective, rel=1e-6)
+            x, _, d, k, _ = inst[i]
+            gm = means_to_host(*b.get_means(i), k, d)
+            assert np.array_equal(gm.indptr, st.means_out.indptr)
+            assert np.array_equal(gm.indices, st.means_out.indices)
+            np.testing.assert_allclose(gm.values, st.means_out.values, rtol=1e-6, atol=0)
+    b.close()
+
+
+def test_batch_rejects_bad_arguments():
+    x = datagen.generate(300, 200, 10.0, 1, 30, 1.1, 7)
+    dx = to_dev(x)
+    with pytest.raises(ivf.IvfError):
+        ivf.IVFBatch([(dx[0], dx[1], dx[2], 200)], [301])        # k > n
+    b = ivf.IVFBatch([(dx[0], dx[1], dx[2], 200)], [5])
+    with pytest.raises(ivf.IvfError):
+        b.iterate(1, [i32(np.full(300, -1, np.int32))])          # no means yet
+    with pytest.raises(ivf.IvfError):
+        b.set_slack(-1.0, 0)
+    b.close()

@@ -118,17 +118,34 @@ def _csv_rows(path):
         return list(csv.DictReader(f))
 
 
-def summarize_trace(stats_csv, out_txt, command):
+def summarize_trace(stats_csv, out_txt, command, note=""):
     """Text summary of a rocprofv3 --kernel-trace --stats run."""
     rows = _csv_rows(stats_csv)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    lines = ["# rocprofv3 kernel statistics", "# command: " + command, "",
+    lines = ["# rocprofv3 kernel statistics", "# command: " + command]
+    if note:
+        lines.append("# " + note)
+    lines += ["",
              "%-40s %6s %14s %14s %7s" % ("kernel", "calls", "total_ms", "avg_ms", "pct")]
     for r in rows[:25]:
         name = r["Name"].replace("ivf::(anonymous namespace)::", "").split("(")[0]
         lines.append("%-40s %6s %14.3f %14.3f %7.2f" % (
             name[:40], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
             float(r["AverageNs"]) / 1e6, float(r["Percentage"])))
+    trace_csv = stats_csv.replace("kernel_stats", "kernel_trace")
+    if os.path.exists(trace_csv):
+        top = rows[0]["Name"]
+        launches = [r for r in _csv_rows(trace_csv) if r["Kernel_Name"] == top]
+        ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in launches]
+        short = top.replace("ivf::(anonymous namespace)::", "").split("(")[0]
+        lines += ["", "%s launches in order (ms): %s" % (short, ", ".join("%.3f" % v for v in ms))]
+        if len(ms) > 1:
+            lines.append("%s average over the launches after the first (the first iteration "
+                         "starts from the seed means): %.3f ms" % (short, sum(ms[1:]) / (len(ms) - 1)))
+        r0 = launches[0]
+        lines.append("%s resources: VGPR %s, AGPR %s, SGPR %s, LDS %s bytes, workgroup %s, grid %s"
+                     % (short, r0["VGPR_Count"], r0["Accum_VGPR_Count"], r0["SGPR_Count"],
+                        r0["LDS_Block_Size"], r0["Workgroup_Size_X"], r0["Grid_Size_X"]))
     with open(out_txt, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -160,9 +177,159 @@ def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, comman
     return out
 
 
+BATCH_METRIC = "aggregate sparse mult-adds/s, 96 batched instances (uneven N, D, k; restarts)"
+
+
+def run_batched(args):
+    """The many-instance workload: 96 instances (48 object sets once, 6 sets
+    with 8 restarts each), N, D, lambda, s and k drawn per set; one batched
+    walk launch per Lloyd iteration, the iteration replayed from HIP graphs.
+    One step = one iteration of all 96 instances.  The warmup covers the two
+    eager iterations, the tile autotuner and the recording of the graphs."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2002_09094_amd as ivf
+
+    dev = "cuda:0"
+    inst = datagen.batched_instances()
+    data = {}
+    for w, _ in inst:
+        if w.name not in data:
+            x = w.generate()
+            xd = (torch.from_numpy(x.indptr).to(dev), torch.from_numpy(x.indices).to(dev),
+                  torch.from_numpy(x.values).to(dev))
+            data[w.name] = (x, xd)
+    nnz_total = sum(data[w.name][0].nnz for w, _ in inst)
+    log("generated %d object sets for %d instances, %d objects, %d nonzeros over instances"
+        % (len(data), len(inst), sum(w.n for w, _ in inst), nnz_total))
+    b = ivf.IVFBatch([(*data[w.name][1], w.d) for w, _ in inst], [w.k for w, _ in inst],
+                     valtype=args.valtype, cluster_range=args.cluster_range,
+                     waves_per_wg=args.waves)
+    b.init_seeds([torch.from_numpy(w.seeds(data[w.name][0], restart=r).astype(np.int32)).to(dev)
+                  for w, r in inst])
+    assigns = [torch.full((w.n,), -1, dtype=torch.int32, device=dev) for w, _ in inst]
+    warmup = max(args.warmup, 3)
+    for r in range(warmup):
+        st = b.iterate(1, assigns)[0]
+        log("warmup %d: batch iteration %.1f ms (walk %.1f), M=%.3e, plan %s"
+            % (r, st[0]["assign_ms"], st[0]["walk_ms"], sum(s["mult_adds"] for s in st), b.plan))
+    torch.cuda.synchronize()
+    per = []
+    t_start = time.perf_counter()
+    for r in range(args.steps):
+        st = b.iterate(1, assigns)[0]
+        per.append(st)
+        log("step %d: batch iteration %.1f ms (walk %.1f), M=%.3e, changed=%d, rescored=%d"
+            % (r, st[0]["assign_ms"], st[0]["walk_ms"], sum(s["mult_adds"] for s in st),
+               sum(s["changed"] for s in st), sum(s["rescored"] for s in st)))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    plan = b.plan
+    tuning = b.tuning
+    log("autotuner (clusters per tile, waves, walk ms): %s" % tuning)
+
+    mult = sum(s["mult_adds"] for st in per for s in st)
+    walk_avg_s = sum(st[0]["walk_ms"] for st in per) / len(per) / 1e3
+    wb = [sum(walk_bytes(s["mult_adds"], data[w.name][0].nnz, w.n, args.valtype)
+              for s, (w, _) in zip(st, inst)) for st in per]
+    achieved = (sum(wb) / len(wb)) / walk_avg_s / 1e9
+
+    # per-instance exactness, outside the timed region: one more iteration,
+    # a seeded sample of every instance re-assigned by the FP64 oracle from
+    # the same means and previous assignment
+    import oracle
+    before = []
+    for i, (w, _) in enumerate(inst):
+        ptr, idx, val = (t.cpu().numpy() for t in b.get_means(i))
+        before.append((oracle.Means(w.k, w.d, ptr, idx, val), assigns[i].cpu().numpy()))
+    b.iterate(1, assigns)
+    exact, sampled = 0, 0
+    t_or = time.perf_counter()
+    or_mult = 0
+    for i, (w, r) in enumerate(inst):
+        x = data[w.name][0]
+        m = min(w.n, 96)
+        rows = np.sort(datagen.perm_prefix(w.n, m, w.seed + 1000 * r, stream=7))
+        ar = oracle.assign(x.subset(rows), before[i][0], before[i][1][rows])
+        got = assigns[i].cpu().numpy()[rows]
+        exact += int(np.array_equal(got, ar.assign))
+        sampled += m
+        or_mult += ar.mult_adds
+    t_or = time.perf_counter() - t_or
+    log("oracle check: %d of %d instances identical on %d sampled objects (%.1fs)"
+        % (exact, len(inst), sampled, t_or))
+    out = {
+        "metric": BATCH_METRIC,
+        "value": mult / t_total,
+        "unit": "mult-adds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * t_total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.valtype,
+        "data": "synthetic",
+        "config": {"workload": "batched96", "instances": len(inst), "object_sets": len(data),
+                   "objects": sum(w.n for w, _ in inst), "nnz": nnz_total,
+                   "k_range": [min(w.k for w, _ in inst), max(w.k for w, _ in inst)],
+                   "valtype": args.valtype, "plan": plan,
+                   "autotuner": [{"clusters_per_tile": t[0], "waves": t[1], "walk_ms": t[2]}
+                                 for t in tuning]},
+        "iter_per_s": args.steps / t_total,
+        "mult_adds_per_iter": mult / len(per),
+        "walk_ms": 1e3 * walk_avg_s,
+        "iteration_ms": sum(st[0]["assign_ms"] for st in per) / len(per),
+        "instances_identical_to_oracle": exact,
+        "oracle_sampled_objects": sampled,
+        "certified_fraction": (sum(s["certified"] for st in per for s in st)
+                               / (len(per) * sum(w.n for w, _ in inst))),
+        "roofline": {
+            "kernel": "k_walk_batch",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+        },
+    }
+    b.close()
+    if not args.no_cpu_baseline:
+        # the oracle's assignment walk on the first objects of successive
+        # instances (their means before the check iteration) until about
+        # --cpu-seconds of CPU work
+        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+        cm, ct, used, objs = 0, 0.0, 0, 0
+        for i, (w, _) in enumerate(inst):
+            x = data[w.name][0]
+            m = min(w.n, 4000)
+            rows = np.arange(m)
+            t = time.perf_counter()
+            ar = oracle.assign(x.subset(rows), before[i][0], before[i][1][rows], threads=threads)
+            ct += time.perf_counter() - t
+            cm += ar.mult_adds
+            used += 1
+            objs += m
+            if ct >= args.cpu_seconds:
+                break
+        log("cpu baseline: %d objects of %d instances, %.3e mult-adds in %.1fs"
+            % (objs, used, cm, ct))
+        out["cpu_baseline"] = {
+            "value": cm / ct, "unit": "mult-adds/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle assignment walk of the first %d objects of each of the "
+                      "first %d instances (%d objects) against their current means, %.1fs"
+                      % (4000, used, objs, ct)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
-        summarize_trace(sys.argv[2], sys.argv[3], sys.argv[4])
+        summarize_trace(*sys.argv[2:6])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
         print(json.dumps(summarize_counters(*sys.argv[2:8])))
@@ -185,6 +352,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched96":
+        run_batched(args)
+        return
 
     import numpy as np
     import torch

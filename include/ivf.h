@@ -272,8 +272,10 @@ ivf_status ivf_batch_set_means(ivf_batch* b, int32_t inst, const ivf_means* M);
  * assignment in, new one out, -1 = unassigned); the same pointers should be
  * passed on every call (new pointers force the graphs to be recorded again).
  * stats (host, [iters * count], iteration-major) may be NULL; when given, each
- * entry holds that instance's assignment and update fields, and assign_ms the
- * device time of the whole batch iteration.  Synchronises before returning.
+ * entry holds that instance's assignment and update fields, assign_ms the
+ * device time of the whole batch iteration and walk_ms that of its one walk
+ * launch, read from the device real-time clock just before and after it
+ * (both the same for every instance).  Synchronises before returning.
  */
 ivf_status ivf_batch_iterate(ivf_batch* b, int32_t iters, int32_t* const* assign,
                              ivf_stats* stats);
@@ -298,6 +300,16 @@ ivf_status ivf_batch_set_slack(ivf_batch* b, double frac, int64_t abs_entries);
  * iteration was recorded, plan[7] replays redone after a capacity overflow.
  */
 ivf_status ivf_batch_get_plan(const ivf_batch* b, int32_t plan[8]);
+
+/*
+ * ivf_batch_get_tuning: what the autotuner measured (host outputs).  *count
+ * receives the number of candidates timed (0 before it ran or when the tile
+ * shape was given); the first min(cap, *count) entries are written:
+ * shapes[2i], shapes[2i+1] = clusters per tile, waves per workgroup, and
+ * ms[i] = the batched walk's device time with that shape.
+ */
+ivf_status ivf_batch_get_tuning(const ivf_batch* b, int32_t cap, int32_t* shapes, float* ms,
+                                int32_t* count);
 
 /* Frees the batch, its instances and its stream if it created one. */
 void ivf_batch_destroy(ivf_batch* b);

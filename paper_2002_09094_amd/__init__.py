@@ -291,6 +291,17 @@ class IVFBatch:
                 "recoveries")
         return dict(zip(keys, list(plan)))
 
+    @property
+    def tuning(self):
+        """[(clusters per tile, waves, walk ms)] the autotuner measured."""
+        cap = 16
+        shapes = (ctypes.c_int32 * (2 * cap))()
+        ms = (ctypes.c_float * cap)()
+        n = ctypes.c_int32()
+        _lib.check_batch(_lib.get().ivf_batch_get_tuning(self._b, cap, shapes, ms,
+                                                         ctypes.byref(n)), self._b)
+        return [(shapes[2 * i], shapes[2 * i + 1], ms[i]) for i in range(min(n.value, cap))]
+
     def close(self):
         if getattr(self, "_b", None):
             _lib.get().ivf_batch_destroy(self._b)

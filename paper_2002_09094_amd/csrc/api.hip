@@ -154,6 +154,8 @@ struct ivf_handle {
     // clusters
     int64_t *size = nullptr, *cstart = nullptr, *newcnt = nullptr, *scal = nullptr;
     double *nrm = nullptr, *objpart = nullptr;
+    int64_t* norm_items = nullptr;
+    double* norm_part = nullptr;
     // assignment
     RangeRec* rec = nullptr;
     int32_t* prev = nullptr;
@@ -200,7 +202,7 @@ void free_handle(ivf_handle* h) {
     if (h->slab) (void)hipFree(h->slab);
     h->slab = nullptr;
     dfree(h->size); dfree(h->cstart); dfree(h->newcnt); dfree(h->scal);
-    dfree(h->nrm); dfree(h->objpart);
+    dfree(h->nrm); dfree(h->objpart); dfree(h->norm_items); dfree(h->norm_part);
     dfree(h->rec); dfree(h->prev); dfree(h->seed_assign); dfree(h->rho); dfree(h->best);
     dfree(h->second); dfree(h->best_id); dfree(h->flags); dfree(h->rescore_list);
     dfree(h->part); dfree(h->dscal); dfree(h->cnt);
@@ -371,6 +373,7 @@ ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
     a.seg_j = h->sc->seg_j; a.seg_t = h->sc->seg_t;
     a.size = h->size; a.cstart = h->cstart; a.nrm = h->nrm; a.objpart = h->objpart;
     a.newcnt = h->newcnt; a.scal = h->scal;
+    a.norm_items = h->norm_items; a.norm_part = h->norm_part;
     a.old_ptr = h->mm_ptr[o]; a.old_idx = h->mm_idx[o]; a.old_val = h->mm_val[o];
     a.new_ptr = h->mm_ptr[nb];
     a.cnt = h->cnt;
@@ -559,6 +562,8 @@ ivf_status alloc_handle(ivf_handle* h) {
     HIPCHK(h, dalloc(&h->scal, 4));
     HIPCHK(h, dalloc(&h->nrm, k));
     HIPCHK(h, dalloc(&h->objpart, k));
+    HIPCHK(h, dalloc(&h->norm_items, (int64_t)k + 1));
+    HIPCHK(h, dalloc(&h->norm_part, 2 * norm_item_bound(k, h->nnz)));
     for (int b = 0; b < 2; ++b) {
         HIPCHK(h, dalloc(&h->mm_ptr[b], (int64_t)k + 1));
         HIPCHK(h, hipMemsetAsync(h->mm_ptr[b], 0, sizeof(int64_t) * ((size_t)k + 1), h->stream));
@@ -721,7 +726,13 @@ struct ivf_batch {
     int32_t recoveries = 0;   // replays whose new means overflowed a fixed capacity
     int32_t captures = 0;     // times the iteration was recorded
     std::vector<float> tune_ms;   // autotuner: walk time of each candidate tried
+    std::vector<int32_t> tune_shape;   // and its (clusters per tile, waves) pairs
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // device real-time clock read just before and just after the batched walk:
+    // kernel nodes, so graph replays time the walk too
+    unsigned long long* d_stamp = nullptr;
+    unsigned long long* d_work = nullptr;   // work-item counter of the batched walk
+    int clock_khz = 0;
     std::string err;
 };
 
@@ -740,6 +751,10 @@ ivf_status bfail(ivf_batch* b, ivf_status st, const std::string& msg) {
             return bfail((b), e_ == hipErrorOutOfMemory ? IVF_ERR_OOM : IVF_ERR_HIP,     \
                          std::string(#call) + ": " + hipGetErrorString(e_));             \
     } while (0)
+
+__global__ void k_stamp(unsigned long long* out) {
+    if (threadIdx.x == 0) *out = wall_clock64();
+}
 
 void drop_graphs(ivf_batch* b) {
     for (auto& e : b->exec)
@@ -812,24 +827,28 @@ ivf_status batch_plan(ivf_batch* b, int32_t kr_max, int32_t waves) {
 // Autotuner: time the batched walk on the current means for every candidate
 // (clusters per tile, waves per workgroup) and keep the fastest.
 ivf_status batch_autotune(ivf_batch* b) {
-    static const int32_t cand[][2] = {{640, 8}, {1280, 8}, {1280, 4}, {2560, 4}, {2560, 8}};
+    // 640-wide tiles measured slowest on every mix tried; wider tiles favour
+    // batches whose k spread past one 1280-wide range
+    static const int32_t cand[][2] = {{1280, 8}, {2560, 4}, {2560, 8}, {5120, 4}};
     const int32_t count = (int32_t)b->h.size();
     float best = 1e30f;
-    int bi = 1;
+    int bi = 0;
     b->tune_ms.clear();
+    b->tune_shape.clear();
     for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])); ++c) {
         ivf_status st = batch_plan(b, cand[c][0], cand[c][1]);
         if (st != IVF_OK) return st;
         float ms = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {   // the first launch warms the caches
-            BHIP(b, hipEventRecord(b->ev[0], b->stream));
-            BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, count, b->tile_stride,
-                                      b->opt.valtype, b->waves, b->grid, b->stream));
-            BHIP(b, hipEventRecord(b->ev[1], b->stream));
-            BHIP(b, hipEventSynchronize(b->ev[1]));
-            BHIP(b, hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
-        }
+        BHIP(b, hipEventRecord(b->ev[0], b->stream));
+        BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, count, b->tile_stride,
+                                  b->opt.valtype, b->waves, b->grid, b->d_work,
+                                  b->stream));
+        BHIP(b, hipEventRecord(b->ev[1], b->stream));
+        BHIP(b, hipEventSynchronize(b->ev[1]));
+        BHIP(b, hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
         b->tune_ms.push_back(ms);
+        b->tune_shape.push_back(cand[c][0]);
+        b->tune_shape.push_back(cand[c][1]);
         if (ms < best) { best = ms; bi = c; }
     }
     b->tuned = true;
@@ -847,8 +866,11 @@ ivf_status batch_iteration(ivf_batch* b, int32_t* const* assign, bool eager) {
         HIPCHK(h, hipMemcpyAsync(h->prev, assign[i], sizeof(int32_t) * (size_t)h->n,
                                  hipMemcpyDeviceToDevice, s));
     }
+    k_stamp<<<1, 64, 0, s>>>(b->d_stamp);
     BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, count, b->tile_stride, b->opt.valtype,
-                              b->waves, b->grid, s));
+                              b->waves, b->grid, b->d_work, s));
+    k_stamp<<<1, 64, 0, s>>>(b->d_stamp + 1);
+    BHIP(b, hipGetLastError());
     for (int32_t i = 0; i < count; ++i) {
         ivf_status st = assign_finish(b->h[i], assign[i]);
         if (st != IVF_OK) return bfail(b, st, b->h[i]->err);
@@ -1201,6 +1223,10 @@ ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
         BHIP(b, hipMemcpy(b->d_cnt, cp.data(), sizeof(Counters*) * count, hipMemcpyHostToDevice));
     }
     for (auto& e : b->ev) BHIP(b, hipEventCreate(&e));
+    BHIP(b, dalloc(&b->d_stamp, 2));
+    BHIP(b, dalloc(&b->d_work, 1));
+    BHIP(b, hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev));
+    if (b->clock_khz <= 0) return bail(bfail(b, IVF_ERR_HIP, "no device wall clock rate"));
     ivf_status st = batch_plan(b, oi.cluster_range, o.waves_per_wg > 0 ? o.waves_per_wg : 8);
     if (st != IVF_OK) return bail(st);
     *out = b;
@@ -1293,6 +1319,9 @@ ivf_status ivf_batch_iterate(ivf_batch* b, int32_t iters, int32_t* const* assign
         }
         if (stats) {
             BHIP(b, hipStreamSynchronize(b->stream));
+            unsigned long long st[2] = {0, 0};
+            BHIP(b, hipMemcpy(st, b->d_stamp, sizeof(st), hipMemcpyDeviceToHost));
+            const float wms = (float)((double)(st[1] - st[0]) / (double)b->clock_khz);
             for (int32_t i = 0; i < count; ++i) {
                 ivf_handle* h = b->h[i];
                 ivf_stats* s = stats + (size_t)r * count + i;
@@ -1308,7 +1337,8 @@ ivf_status ivf_batch_iterate(ivf_batch* b, int32_t iters, int32_t* const* assign
                 s->objective_exact = ds[1];
                 s->empty_clusters = (int64_t)c.empty;
                 s->nnz_means = nnz_now;
-                s->assign_ms = ms;   // the whole iteration of the batch
+                s->assign_ms = ms;    // the whole iteration of the batch
+                s->walk_ms = wms;     // the one walk launch of the batch
                 s->update_ms = 0.f;
             }
         }
@@ -1346,6 +1376,19 @@ ivf_status ivf_batch_get_plan(const ivf_batch* b, int32_t plan[8]) {
     return IVF_OK;
 }
 
+ivf_status ivf_batch_get_tuning(const ivf_batch* b, int32_t cap, int32_t* shapes, float* ms,
+                                int32_t* count) {
+    if (!b || !count || cap < 0 || (cap > 0 && (!shapes || !ms))) return IVF_ERR_ARG;
+    const int32_t n = (int32_t)b->tune_ms.size();
+    *count = n;
+    for (int32_t i = 0; i < n && i < cap; ++i) {
+        shapes[2 * i] = b->tune_shape[2 * i];
+        shapes[2 * i + 1] = b->tune_shape[2 * i + 1];
+        ms[i] = b->tune_ms[i];
+    }
+    return IVF_OK;
+}
+
 void ivf_batch_destroy(ivf_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
@@ -1365,6 +1408,8 @@ void ivf_batch_destroy(ivf_batch* b) {
     dfree(b->d_cnt);
     for (auto& e : b->ev)
         if (e) (void)hipEventDestroy(e);
+    dfree(b->d_stamp);
+    dfree(b->d_work);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

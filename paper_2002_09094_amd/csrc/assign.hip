@@ -247,8 +247,23 @@ __device__ inline void zero_tile(float* tile, int stride, int lane) {
         *reinterpret_cast<float4*>(tile + s) = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// The whole wave claims its next work item: one atomic from lane 0, whose
+// result every lane takes with readfirstlane after the lanes reconverge, so
+// the caller's loop test is scalar and all 64 lanes leave the loop together.
+__device__ inline int64_t claim_item(unsigned long long* ctr, int lane) {
+    unsigned long long v = 0ull;
+    if (lane == 0) v = atomicAdd(ctr, 1ull);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Waves per SIMD the walk is compiled for (the register budget): 16-bit
+// values fit 8 without spilling; the FP32 walk keeps 6 (more waves measured no
+// faster: it is bound by L2 capacity, not by latency hiding).
 template <int VT>
-__global__ __launch_bounds__(kWave * kMaxWaves) void k_walk(WalkArgs a) {
+__global__ __launch_bounds__(kWave * kMaxWaves)
+__attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(WalkArgs a) {
     extern __shared__ float4 lds4[];
     const int lane = lane_id();
     // wave index made provably uniform, so every loop below has uniform bounds
@@ -258,27 +273,47 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_walk(WalkArgs a) {
     float* tile = reinterpret_cast<float*>(lds4) + (int64_t)wv * a.tile_stride;
     zero_tile(tile, a.tile_stride, lane);
     const int64_t total = a.items_per_range * a.R;
-    // items in ascending order, round robin over the waves: all waves sweep
-    // the ranges in the same order, so a range's slices stay hot in the caches
-    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves)
-        walk_item<VT>(a, w, tile, lane);
+    // items in ascending order: all waves sweep the ranges in the same order,
+    // so a range's slices stay hot in the caches
+    if constexpr (VT == IVF_VAL_F32) {
+        // claimed from the counter: keeps the waves in one window of items
+        // (2 % faster than the round robin at 8M documents x k = 10,000)
+        for (;;) {
+            const int64_t w = claim_item(&a.cnt->work, lane);
+            if (w >= total) break;
+            walk_item<VT>(a, w, tile, lane);
+        }
+    } else {
+        // static round robin: at 8 waves per SIMD the claim would spill
+        // registers (16-bit walks measured 19 % slower with it)
+        for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves)
+            walk_item<VT>(a, w, tile, lane);
+    }
 }
 
 // Many instances in one persistent launch: item w belongs to the instance b
 // with item_off[b] <= w < item_off[b + 1]; every wave's tile holds the widest
-// range of all instances.
+// range of all instances.  Items are claimed from a counter in ascending
+// order: items of different instances cost very different amounts, and a
+// static round robin let the waves drift apart across ranges and instances
+// (a working set many times one range's); claiming keeps all waves within
+// one window of consecutive items.  Every claim advances the counter, so a
+// wave leaves after at most total + 1 claims.
 template <int VT>
-__global__ __launch_bounds__(kWave * kMaxWaves) void k_walk_batch(const WalkArgs* __restrict__ args,
+__global__ __launch_bounds__(kWave * kMaxWaves)
+__attribute__((amdgpu_waves_per_eu(7, 8))) void k_walk_batch(const WalkArgs* __restrict__ args,
                                                                   const int64_t* __restrict__ item_off,
-                                                                  int32_t count, int32_t tile_stride) {
+                                                                  int32_t count, int32_t tile_stride,
+                                                                  unsigned long long* work) {
     extern __shared__ float4 lds4[];
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
     float* tile = reinterpret_cast<float*>(lds4) + (int64_t)wv * tile_stride;
     zero_tile(tile, tile_stride, lane);
     const int64_t total = item_off[count];
-    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves) {
+    for (;;) {
+        const int64_t w = claim_item(work, lane);
+        if (w >= total) break;
         int32_t lo = 0, hi = count;   // last b with item_off[b] <= w
         while (hi - lo > 1) {
             const int32_t mid = (lo + hi) >> 1;
@@ -464,6 +499,10 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
     if (threadIdx.x == 0) *out = sh[0];
 }
 
+__global__ void k_zero_u64(unsigned long long* p) {
+    if (threadIdx.x == 0) *p = 0ull;
+}
+
 __global__ void k_clear_counters(Counters* c) {
     unsigned long long* p = reinterpret_cast<unsigned long long*>(c);
     const int n = (int)(sizeof(Counters) / sizeof(unsigned long long));
@@ -491,15 +530,16 @@ hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes,
 
 hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int32_t count,
                              int32_t tile_stride, int valtype, int waves, int grid,
-                             hipStream_t s) {
+                             unsigned long long* work, hipStream_t s) {
     const dim3 blk(kWave * waves);
     const size_t lds = (size_t)waves * tile_stride * 4;
+    k_zero_u64<<<1, 64, 0, s>>>(work);
     if (valtype == IVF_VAL_F32)
-        k_walk_batch<IVF_VAL_F32><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride);
+        k_walk_batch<IVF_VAL_F32><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride, work);
     else if (valtype == IVF_VAL_BF16)
-        k_walk_batch<IVF_VAL_BF16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride);
+        k_walk_batch<IVF_VAL_BF16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride, work);
     else
-        k_walk_batch<IVF_VAL_F16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride);
+        k_walk_batch<IVF_VAL_F16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride, work);
     return hipGetLastError();
 }
 

@@ -57,10 +57,11 @@ hipError_t launch_clear_counters(Counters* c, hipStream_t s);
 hipError_t walk_set_lds_limit(int lds_bytes);
 const void* walk_kernel_ptr(int valtype);
 const void* walk_batch_kernel_ptr(int valtype);
-// Walk of many instances in one persistent launch (args, item_off: device).
+// Walk of many instances in one persistent launch (args, item_off: device;
+// work: a device counter the launch resets and the waves claim items from).
 hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int32_t count,
                              int32_t tile_stride, int valtype, int waves, int grid,
-                             hipStream_t s);
+                             unsigned long long* work, hipStream_t s);
 hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes, int grid,
                        hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
@@ -97,6 +98,11 @@ hipError_t launch_term_shift(const int32_t* x_idx, const float* x_val, int64_t n
                              int32_t* emin, int32_t* emax, int32_t* count, int16_t* shift,
                              Counters* cnt, hipStream_t s);
 
+// Segments per work item of the update's norm pass, and the most items any
+// update of k clusters over nnz object entries can have.
+constexpr int64_t kNormChunk = 4096;
+inline int64_t norm_item_bound(int64_t k, int64_t nnz) { return k + nnz / kNormChunk + 1; }
+
 struct UpdateArgs {
     int64_t n, d, nnz;
     int32_t k;
@@ -124,6 +130,8 @@ struct UpdateArgs {
     double* objpart;    // [k]
     int64_t* newcnt;    // [k]
     int64_t* scal;      // device scalars: [0] valid entries, [1] segments
+    int64_t* norm_items;  // [k + 1] norm work items per cluster, then their offsets
+    double* norm_part;    // [2 * norm_item_bound(k, nnz)] per item: sum w^2, mu(old) . s
     // old means (mean-major) and new means
     const int64_t* old_ptr;
     const int32_t* old_idx;

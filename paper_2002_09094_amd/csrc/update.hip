@@ -269,33 +269,49 @@ __device__ inline double seg_value(const unsigned long long* acc, const int32_t*
     return ldexp((double)acc[s], (int)shift[seg_t[s]]);
 }
 
-// One wave per cluster: FP64 norm of w = s / |C_j| (lane-strided partials,
-// then a fixed butterfly: deterministic), the cluster's share of the exact
-// objective mu_j(old) . s_j, and the new row length.
-__global__ __launch_bounds__(kThreads) void k_norms(UpdateArgs a) {
-    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = lane_id();
-    if (j >= a.k) return;
-    const int64_t nj = a.size[j];
-    if (nj == 0) {
-        if (lane == 0) {
-            a.newcnt[j] = a.old_ptr[j + 1] - a.old_ptr[j];
-            a.nrm[j] = 0.0;
-            a.objpart[j] = 0.0;
-            atomicAdd(&a.cnt->empty, 1ull);
-        }
+// The norm pass works on fixed chunks of kNormChunk segments, so its
+// parallelism does not depend on k (a few huge clusters or many small ones).
+// Work items per cluster: ceil(segments / kNormChunk) for a cluster with members.
+__global__ void k_norm_items(const int64_t* __restrict__ size, const int64_t* __restrict__ cstart,
+                             int32_t k, int64_t* __restrict__ items) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > k) return;
+    if (j == k) {
+        items[k] = 0;
         return;
     }
-    const int64_t s0 = a.cstart[j], s1 = a.cstart[j + 1];
+    const int64_t len = cstart[j + 1] - cstart[j];
+    items[j] = size[j] > 0 ? (len + kNormChunk - 1) / kNormChunk : 0;
+}
+
+// One wave per work item (the scanned item offsets locate its cluster):
+// partial FP64 sums over one chunk of the cluster's segments of w^2, with
+// w = s / |C_j|, and of mu_j(old) . s (the exact objective's share).
+// Lane-strided partials and a fixed butterfly: deterministic.
+__global__ __launch_bounds__(kThreads) void k_norm_parts(UpdateArgs a) {
+    const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = lane_id();
+    if (it >= a.norm_items[a.k]) return;
+    int64_t lo = 0, hi = a.k;   // last cluster j with norm_items[j] <= it
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.norm_items[mid] <= it) lo = mid; else hi = mid;
+    }
+    const int64_t j = lo;
+    const int64_t c = it - a.norm_items[j];
+    const int64_t s0 = a.cstart[j] + c * kNormChunk;
+    const int64_t s1 = min(a.cstart[j + 1], s0 + kNormChunk);
     const int64_t ob = a.old_ptr[j], oe = a.old_ptr[j + 1];
-    const double dn = (double)nj;
+    const double dn = (double)a.size[j];
     double ss = 0.0, op = 0.0;
+    int64_t from = ob;   // a lane's terms ascend, so its old-row cursor only moves on
     for (int64_t s = s0 + lane; s < s1; s += kWave) {
         const double sv = seg_value(a.seg_acc, a.seg_t, a.shift, s);
         const double w = sv / dn;
         ss += w * w;
         const int32_t t = a.seg_t[s];
-        const int64_t p = lower_bound_i32(a.old_idx, ob, oe, t);
+        const int64_t p = lower_bound_i32(a.old_idx, from, oe, t);
+        from = p;
         if (p < oe && a.old_idx[p] == t) op += a.old_val[p] * sv;
     }
 #pragma unroll
@@ -304,10 +320,32 @@ __global__ __launch_bounds__(kThreads) void k_norms(UpdateArgs a) {
         op += __shfl_xor(op, o, kWave);
     }
     if (lane == 0) {
-        a.nrm[j] = sqrt(ss);
-        a.objpart[j] = op;
-        a.newcnt[j] = s1 - s0;
+        a.norm_part[2 * it] = ss;
+        a.norm_part[2 * it + 1] = op;
     }
+}
+
+// One thread per cluster: its items' partials summed in item order, the FP64
+// norm, the objective share and the new row length; a cluster without
+// members keeps its row.
+__global__ void k_norm_final(UpdateArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.k) return;
+    if (a.size[j] == 0) {
+        a.newcnt[j] = a.old_ptr[j + 1] - a.old_ptr[j];
+        a.nrm[j] = 0.0;
+        a.objpart[j] = 0.0;
+        atomicAdd(&a.cnt->empty, 1ull);
+        return;
+    }
+    double ss = 0.0, op = 0.0;
+    for (int64_t i = a.norm_items[j]; i < a.norm_items[j + 1]; ++i) {
+        ss += a.norm_part[2 * i];
+        op += a.norm_part[2 * i + 1];
+    }
+    a.nrm[j] = sqrt(ss);
+    a.objpart[j] = op;
+    a.newcnt[j] = a.cstart[j + 1] - a.cstart[j];
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill(UpdateArgs a) {
@@ -566,7 +604,12 @@ hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s) {
         HIP_RET(hipGetLastError());
     }
     k_cstart<<<grid_for(a.k + 1), kThreads, 0, s>>>(a.seg_j, a.scal, a.k, a.cstart);
-    k_norms<<<grid_for((int64_t)a.k * kWave), kThreads, 0, s>>>(a);
+    k_norm_items<<<grid_for(a.k + 1), kThreads, 0, s>>>(a.size, a.cstart, a.k, a.norm_items);
+    HIP_RET(hipGetLastError());
+    HIP_RET(exclusive_scan_i64(a.norm_items, a.norm_items, (int64_t)a.k + 1, a.tmp, s));
+    // one wave per item; the item count is bounded by k + nnz / kNormChunk + 1
+    k_norm_parts<<<grid_for(norm_item_bound(a.k, a.nnz) * kWave), kThreads, 0, s>>>(a);
+    k_norm_final<<<grid_for(a.k), kThreads, 0, s>>>(a);
     HIP_RET(hipGetLastError());
     // new row pointers: exclusive scan of k + 1 counts (the last is 0)
     k_zero_i64<<<1, 64, 0, s>>>(a.newcnt + a.k, 1);

@@ -177,6 +177,44 @@ def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, comman
     return out
 
 
+def summarize_pmc(out_txt, command, *csvs):
+    """Text summary of rocprofv3 --pmc passes over the walk: the counters of
+    its last dispatch in each pass and the ratios read from them."""
+    import collections
+    vals = collections.OrderedDict()
+    for path in csvs:
+        rows = [r for r in _csv_rows(path) if "k_walk" in r["Kernel_Name"]]
+        last = max(int(r["Dispatch_Id"]) for r in rows)
+        for r in rows:
+            if int(r["Dispatch_Id"]) == last:
+                vals[r["Counter_Name"]] = float(r["Counter_Value"])
+    lines = ["# rocprofv3 counters of the steady-state walk launch (last k_walk dispatch of each pass)",
+             "# commands: " + command, ""]
+    for k, v in vals.items():
+        lines.append("%-34s %.4e" % (k, v))
+    g = vals.get
+    lines.append("")
+    if g("TCC_HIT_sum") is not None and g("TCC_MISS_sum") is not None:
+        h, m = g("TCC_HIT_sum"), g("TCC_MISS_sum")
+        lines.append("L2 hit rate (requests): %.3f" % (h / (h + m)))
+    if g("SQ_WAIT_ANY") and g("SQ_WAVE_CYCLES"):
+        lines.append("wave cycles waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES): %.3f"
+                     % (g("SQ_WAIT_ANY") / g("SQ_WAVE_CYCLES")))
+    if g("SQ_WAIT_INST_LDS") and g("SQ_WAVE_CYCLES"):
+        lines.append("wave cycles waiting on LDS: %.3f" % (g("SQ_WAIT_INST_LDS") / g("SQ_WAVE_CYCLES")))
+    if g("SQ_LDS_BANK_CONFLICT") and g("SQ_LDS_IDX_ACTIVE"):
+        lines.append("LDS bank-conflict cycles / LDS active cycles: %.3f"
+                     % (g("SQ_LDS_BANK_CONFLICT") / g("SQ_LDS_IDX_ACTIVE")))
+    if g("TCP_TCC_READ_REQ_LATENCY_sum") and g("TCP_TCC_READ_REQ_sum"):
+        lines.append("average L2 read latency seen by L1 (cycles): %.0f"
+                     % (g("TCP_TCC_READ_REQ_LATENCY_sum") / g("TCP_TCC_READ_REQ_sum")))
+    if g("TCP_TCC_READ_REQ_sum") and g("TCP_TOTAL_CACHE_ACCESSES_sum"):
+        lines.append("L1 accesses that go to L2: %.3f"
+                     % (g("TCP_TCC_READ_REQ_sum") / g("TCP_TOTAL_CACHE_ACCESSES_sum")))
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 BATCH_METRIC = "aggregate sparse mult-adds/s, 96 batched instances (uneven N, D, k; restarts)"
 
 
@@ -330,6 +368,9 @@ def run_batched(args):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
         summarize_trace(*sys.argv[2:6])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-pmc":
+        summarize_pmc(*sys.argv[2:])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
         print(json.dumps(summarize_counters(*sys.argv[2:8])))

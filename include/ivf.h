@@ -194,8 +194,9 @@ ivf_status ivf_get_scores(ivf_handle* h, float* best, int32_t* best_id, float* s
 /*
  * ivf_get_plan: the launch plan chosen by ivf_build: plan[0] clusters per
  * range (k_r), plan[1] number of ranges, plan[2] waves per workgroup,
- * plan[3] objects per work item, plan[4] FP64 re-score range size,
- * plan[5] FP64 re-score ranges, plan[6] LDS bytes per workgroup.
+ * plan[3] objects per work item, plan[4] and plan[5] clusters per range and
+ * ranges of the FP64 re-score's FP32 candidate walk (the walk's own),
+ * plan[6] LDS bytes per workgroup.
  */
 ivf_status ivf_get_plan(const ivf_handle* h, int32_t plan[7]);
 

@@ -56,7 +56,7 @@ def plan_shape(k, **opts):
     o = _options(**opts)
     plan = (ctypes.c_int32 * 7)()
     check(_lib.get().ivf_plan_shape(int(k), ctypes.byref(o), plan))
-    keys = ("k_r", "ranges", "waves", "chunk", "k_r64", "ranges64", "lds_bytes")
+    keys = ("k_r", "ranges", "waves", "chunk", "rescore_k_r", "rescore_ranges", "lds_bytes")
     return dict(zip(keys, list(plan)))
 
 
@@ -144,7 +144,7 @@ class IVFKMeans:
     def plan(self):
         plan = (ctypes.c_int32 * 7)()
         check(_lib.get().ivf_get_plan(self._h, plan), self._h)
-        keys = ("k_r", "ranges", "waves", "chunk", "k_r64", "ranges64", "lds_bytes")
+        keys = ("k_r", "ranges", "waves", "chunk", "rescore_k_r", "rescore_ranges", "lds_bytes")
         return dict(zip(keys, list(plan)))
 
     # -- steps -------------------------------------------------------------

@@ -44,13 +44,14 @@ struct Scratch {
     uint32_t* iota = nullptr;
     uint32_t *flag = nullptr, *segpos = nullptr;
     unsigned long long* seg_acc = nullptr;
+    uint2* pay = nullptr;   // update: (term, value) payload sorted by cluster
     int32_t *seg_j = nullptr, *seg_t = nullptr;
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
 
     void release() {
         dfree(keys); dfree(vals); dfree(keys_alt); dfree(vals_alt); dfree(iota);
-        dfree(flag); dfree(segpos); dfree(seg_acc); dfree(seg_j); dfree(seg_t);
+        dfree(flag); dfree(segpos); dfree(seg_acc); dfree(seg_j); dfree(seg_t); dfree(pay);
         if (tmp) (void)hipFree(tmp);
         tmp = nullptr;
         sort_cap = seg_cap = 0;
@@ -73,7 +74,7 @@ struct Scratch {
             sort_cap = cap;
         }
         if (seg_need > seg_cap) {
-            dfree(flag); dfree(segpos); dfree(seg_acc); dfree(seg_j); dfree(seg_t);
+            dfree(flag); dfree(segpos); dfree(seg_acc); dfree(seg_j); dfree(seg_t); dfree(pay);
             seg_cap = 0;
             hipError_t e;
             if ((e = dalloc(&flag, seg_need)) != hipSuccess) return e;
@@ -81,6 +82,7 @@ struct Scratch {
             if ((e = dalloc(&seg_acc, seg_need)) != hipSuccess) return e;
             if ((e = dalloc(&seg_j, seg_need)) != hipSuccess) return e;
             if ((e = dalloc(&seg_t, seg_need)) != hipSuccess) return e;
+            if ((e = dalloc(&pay, seg_need)) != hipSuccess) return e;
             seg_cap = seg_need;
         }
         const size_t need = std::max(radix_tmp_bytes(std::max<int64_t>(sort_cap, 1)),
@@ -106,12 +108,11 @@ struct ObjView {
     const float* x_val = nullptr;
     int64_t n = 0, d = 0, nnz = 0;
     int32_t* xt_obj = nullptr;
-    int32_t* xt_term = nullptr;
-    float* xt_val = nullptr;
+    uint2* xt_tv = nullptr;
     int16_t* shift = nullptr;
     int64_t inexact = 0;
 
-    void release() { dfree(xt_obj); dfree(xt_term); dfree(xt_val); dfree(shift); }
+    void release() { dfree(xt_obj); dfree(xt_tv); dfree(shift); }
 };
 
 }  // namespace
@@ -123,7 +124,7 @@ struct ivf_handle {
     hipStream_t stream = nullptr;
     Plan plan;
     int device = 0, cus = 0;
-    int walk_grid = 0, rescore_grid = 0;
+    int walk_grid = 0, rescore_grid = 0, rescore_waves = 1;
     ObjView* ov = nullptr;
     bool owns_ov = false;
     Scratch* sc = nullptr;
@@ -146,7 +147,6 @@ struct ivf_handle {
     SliceDesc* desc = nullptr;
     int64_t* dsz = nullptr;
     int32_t* cid = nullptr;
-    double* val64 = nullptr;
     void* post = nullptr;
     void* slab = nullptr;
     int64_t slab_cap = 0;      // elements
@@ -196,7 +196,7 @@ void free_handle(ivf_handle* h) {
     for (int b = 0; b < 2; ++b) {
         dfree(h->mm_ptr[b]); dfree(h->mm_idx[b]); dfree(h->mm_val[b]); dfree(h->mm_row[b]);
     }
-    dfree(h->ivf_ptr); dfree(h->desc); dfree(h->dsz); dfree(h->cid); dfree(h->val64);
+    dfree(h->ivf_ptr); dfree(h->desc); dfree(h->dsz); dfree(h->cid);
     if (h->post) (void)hipFree(h->post);
     h->post = nullptr;
     if (h->slab) (void)hipFree(h->slab);
@@ -262,12 +262,11 @@ ivf_status ensure_ivf(ivf_handle* h, int64_t need) {
     if (need > h->ivf_cap) {
         if (h->fixed) return fail(h, IVF_ERR_CAPACITY, "inverted file exceeds the fixed capacity");
         const int64_t cap = std::max<int64_t>(need, h->ivf_cap + h->ivf_cap / 4);
-        dfree(h->cid); dfree(h->val64);
+        dfree(h->cid);
         if (h->post) (void)hipFree(h->post);
         h->post = nullptr;
         h->ivf_cap = 0;
         HIPCHK(h, dalloc(&h->cid, cap));
-        HIPCHK(h, dalloc(&h->val64, cap));
         HIPCHK(h, hipMalloc(&h->post, (size_t)std::max<int64_t>(cap, 1) * 8));
         h->ivf_cap = cap;
     }
@@ -320,7 +319,6 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
     a.desc = h->desc;
     a.dsz = h->dsz;
     a.cid = h->cid;
-    a.val64 = h->val64;
     a.post = h->post;
     a.slab = h->slab;
     a.tmp = h->sc->tmp;
@@ -365,10 +363,9 @@ ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
     UpdateArgs a{};
     a.n = h->n; a.d = h->d; a.nnz = h->nnz; a.k = h->k;
     a.assign = assign;
-    a.xt_obj = h->ov->xt_obj; a.xt_term = h->ov->xt_term; a.xt_val = h->ov->xt_val;
+    a.xt_obj = h->ov->xt_obj; a.xt_tv = h->ov->xt_tv;
     a.shift = h->ov->shift;
-    a.keys = h->sc->keys; a.vals = h->sc->vals; a.keys_alt = h->sc->keys_alt;
-    a.vals_alt = h->sc->vals_alt; a.iota = h->sc->iota;
+    a.keys = h->sc->keys; a.keys_alt = h->sc->keys_alt; a.pay = h->sc->pay;
     a.flag = h->sc->flag; a.segpos = h->sc->segpos; a.seg_acc = h->sc->seg_acc;
     a.seg_j = h->sc->seg_j; a.seg_t = h->sc->seg_t;
     a.size = h->size; a.cstart = h->cstart; a.nrm = h->nrm; a.objpart = h->objpart;
@@ -441,12 +438,12 @@ ivf_status assign_finish(ivf_handle* h, int32_t* assign) {
     HIPCHK(h, launch_merge(m, s));
     if (h->opt.certify) {
         RescoreArgs r{};
-        r.x_ptr = h->ov->x_ptr; r.x_idx = h->ov->x_idx; r.x_val = h->ov->x_val;
-        r.ivf_ptr = h->ivf_ptr; r.cid = h->cid; r.val64 = h->val64;
-        r.k = h->k; r.k_r64 = p.k_r64; r.R64 = p.R64;
+        r.w = walk_args(h);
+        r.mm_ptr = h->mm_ptr[h->cur]; r.mm_idx = h->mm_idx[h->cur]; r.mm_val = h->mm_val[h->cur];
+        r.valtype = h->opt.valtype;
         r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
         r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
-        HIPCHK(h, launch_rescore(r, h->rescore_grid, s));
+        HIPCHK(h, launch_rescore(r, h->rescore_waves, h->rescore_grid, s));
     }
     HIPCHK(h, launch_objective(h->rho, assign, h->prev, h->n, h->part, kObjBlocks, h->dscal,
                                h->cnt, s));
@@ -492,6 +489,15 @@ int occupancy_grid(int cus, const void* kernel, int waves, int lds) {
     return cus * per_cu;
 }
 
+// Launch shape of the FP64 re-score: as many waves per workgroup (each with
+// its own tile) as fit the LDS, up to 8, and a persistent grid.
+void plan_rescore(ivf_handle* h) {
+    const int tile_bytes = h->plan.tile_stride * 4;
+    h->rescore_waves = std::max(1, std::min(8, kLdsBytes / std::max(tile_bytes, 1)));
+    h->rescore_grid = occupancy_grid(h->cus, rescore_kernel_ptr(h->opt.valtype), h->rescore_waves,
+                                     h->rescore_waves * tile_bytes);
+}
+
 // Validation, term-major view and fixed-point scales of one object set.
 ivf_status build_objview(ivf_handle* h, const ivf_csr* X) {
     ObjView* ov = h->ov;
@@ -509,8 +515,7 @@ ivf_status build_objview(ivf_handle* h, const ivf_csr* X) {
     int32_t* rowid = nullptr;
     HIPCHK(h, dalloc(&rowid, nnz));
     HIPCHK(h, dalloc(&ov->xt_obj, nnz));
-    HIPCHK(h, dalloc(&ov->xt_term, nnz));
-    HIPCHK(h, dalloc(&ov->xt_val, nnz));
+    HIPCHK(h, dalloc(&ov->xt_tv, nnz));
     if (nnz > 0) {
         // stable sort of (term, position): positions ascend with objects
         HIPCHK(h, launch_row_ids(X->indptr, n, rowid, h->stream));
@@ -520,7 +525,7 @@ ivf_status build_objview(ivf_handle* h, const ivf_csr* X) {
         HIPCHK(h, radix_sort_pairs(sc->keys, sc->vals, sc->keys_alt, sc->vals_alt, nnz, bits,
                                    sc->tmp, h->stream, sc->iota));
         HIPCHK(h, launch_build_xt(sc->keys, sc->vals, rowid, X->values, nnz, ov->xt_obj,
-                                  ov->xt_term, ov->xt_val, h->stream));
+                                  ov->xt_tv, h->stream));
     }
     int32_t *emin = nullptr, *emax = nullptr, *tcount = nullptr;
     HIPCHK(h, dalloc(&emin, d));
@@ -590,7 +595,7 @@ ivf_status alloc_handle(ivf_handle* h) {
     HIPCHK(h, walk_set_lds_limit(kLdsBytes));
     h->walk_grid = occupancy_grid(h->cus, walk_kernel_ptr(h->opt.valtype), h->plan.waves,
                                   h->plan.lds_bytes);
-    h->rescore_grid = h->cus * 2;
+    plan_rescore(h);
     return IVF_OK;
 }
 
@@ -692,8 +697,8 @@ ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err)
         return IVF_ERR_ARG;
     }
     q.chunk = (o && o->objects_per_item > 0) ? o->objects_per_item : (q.k_r >= 1024 ? 1 : 8);
-    q.k_r64 = std::min<int32_t>(k, 8192);
-    q.R64 = (k + q.k_r64 - 1) / q.k_r64;
+    q.k_r64 = q.k_r;   // the FP64 re-score walks the same ranges
+    q.R64 = q.R;
     *p = q;
     return IVF_OK;
 }
@@ -798,6 +803,7 @@ ivf_status batch_plan(ivf_batch* b, int32_t kr_max, int32_t waves) {
         ivf_handle* h = b->h[i];
         const bool new_ranges = plans[i].R != h->plan.R;
         h->plan = plans[i];
+        plan_rescore(h);
         if (new_ranges) {
             ivf_status st = alloc_plan_buffers(h);
             if (st != IVF_OK) return bfail(b, st, h->err);

@@ -10,9 +10,10 @@
 //              the tile for the next object.
 //   k_merge    Per object: merge the ranges' records, certify the FP32 argmax
 //              with the rounding-error bound, else queue the object for FP64.
-//   k_rescore  Per queued object: recompute every score in FP64 exactly as the
-//              FP64 reference does (ascending terms, ascending clusters within
-//              a term, a separate multiply and add) and apply the argmax rule.
+//   k_rescore  Per queued object: walk it again in FP32, keep the clusters the
+//              bound cannot rule out, score those in FP64 exactly as the FP64
+//              reference does (ascending terms, a separate multiply and add)
+//              and apply the argmax rule.
 //   k_objective / k_sum_final  deterministic FP64 objective and change count.
 #include "ivf_internal.h"
 #include "kernels.h"
@@ -169,6 +170,42 @@ __device__ inline void top2_combine(float& b, int32_t& id, float& s, float ob, i
     }
 }
 
+// Object i's FP32 scores against cluster range r (clusters base .. base + kr)
+// accumulated into the wave's tile, its terms in ascending order.  Returns
+// the posting entries walked (the object's share of M in this range).
+template <int VT>
+__device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r, int32_t base,
+                                            int32_t kr, float* tile, int lane) {
+    const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
+    int32_t m = 0;
+    for (int64_t h0 = hb; h0 < he; h0 += kWave) {
+        const int cnt = (int)min((int64_t)kWave, he - h0);
+        float v = 0.f;
+        int64_t pos = 0, count = 0;
+        if (lane < cnt) {
+            const int32_t t = a.x_idx[h0 + lane];
+            v = a.x_val[h0 + lane];
+            const SliceDesc ds = a.desc[(int64_t)t * a.R + r];
+            pos = ds.pos;
+            count = ds.count;
+        }
+        for (int hh = 0; hh < cnt; ++hh) {
+            const int64_t p = rl64(pos, hh), cn = rl64(count, hh);
+            const float vv = rlf(v, hh);
+            m += (int32_t)cn;
+            if (p >= 0)
+                walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p, p + cn,
+                               vv, tile, base, lane);
+            else
+                walk_dense<VT>(reinterpret_cast<const typename Slab<VT>::T*>(
+                                   reinterpret_cast<const char*>(a.slab) +
+                                   (-p - 1) * (VT == IVF_VAL_F32 ? 4 : 2)),
+                               (kr + 3) >> 2, vv, tile, lane);
+        }
+    }
+    return m;
+}
+
 // One work item: `chunk` consecutive objects against cluster range r, each
 // walked into the wave's tile, its range record written and the tile cleared.
 template <int VT>
@@ -180,33 +217,7 @@ __device__ inline void walk_item(const WalkArgs& a, int64_t w, float* tile, int 
     const int64_t i0 = c * a.chunk;
     const int64_t i1 = min(a.n, i0 + a.chunk);
     for (int64_t i = i0; i < i1; ++i) {
-        const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
-        int32_t m = 0;
-        for (int64_t h0 = hb; h0 < he; h0 += kWave) {
-            const int cnt = (int)min((int64_t)kWave, he - h0);
-            float v = 0.f;
-            int64_t pos = 0, count = 0;
-            if (lane < cnt) {
-                const int32_t t = a.x_idx[h0 + lane];
-                v = a.x_val[h0 + lane];
-                const SliceDesc ds = a.desc[(int64_t)t * a.R + r];
-                pos = ds.pos;
-                count = ds.count;
-            }
-            for (int hh = 0; hh < cnt; ++hh) {
-                const int64_t p = rl64(pos, hh), cn = rl64(count, hh);
-                const float vv = rlf(v, hh);
-                m += (int32_t)cn;
-                if (p >= 0)
-                    walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p,
-                                   p + cn, vv, tile, base, lane);
-                else
-                    walk_dense<VT>(reinterpret_cast<const typename Slab<VT>::T*>(
-                                       reinterpret_cast<const char*>(a.slab) +
-                                       (-p - 1) * (VT == IVF_VAL_F32 ? 4 : 2)),
-                                   (kr + 3) >> 2, vv, tile, lane);
-            }
-        }
+        const int32_t m = accumulate_object<VT>(a, i, r, base, kr, tile, lane);
         // fused top-2 over the tile, clearing it for the next object
         float b = 0.f, s2 = 0.f;
         int32_t id = -1;
@@ -378,83 +389,100 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     if (lane_id() == 0 && m) atomicAdd(&a.cnt->mult, (unsigned long long)m);
 }
 
-// One wave per queued object; an FP64 score tile of k_r64 clusters in LDS.
-__global__ __launch_bounds__(kWave) void k_rescore(RescoreArgs a) {
-    extern __shared__ double t64[];
+// FP64 score of cluster j for the object with nonzeros [hb, he), exactly as
+// the FP64 reference computes it: the products v * u in ascending term order,
+// each a separate FP64 multiply, added one after another (a term absent from
+// mean j adds an exact zero).  u comes from mean j's FP64 row.  The sum runs
+// in a wave-uniform loop, so every lane holds the same value.
+__device__ inline double exact_score(const RescoreArgs& a, int64_t hb, int64_t he, int32_t j,
+                                     int lane) {
+    const int64_t rb = a.mm_ptr[j], re = a.mm_ptr[j + 1];
+    double sum = 0.0;
+    for (int64_t h0 = hb; h0 < he; h0 += kWave) {
+        const int cnt = (int)min((int64_t)kWave, he - h0);
+        double p = 0.0;
+        if (lane < cnt) {
+            const int32_t t = a.w.x_idx[h0 + lane];
+            int64_t lo = rb, hi = re;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (a.mm_idx[mid] < t) lo = mid + 1; else hi = mid;
+            }
+            if (lo < re && a.mm_idx[lo] == t) p = (double)a.w.x_val[h0 + lane] * a.mm_val[lo];
+        }
+        for (int hh = 0; hh < cnt; ++hh)
+            sum = sum + __longlong_as_double(rl64(__double_as_longlong(p), hh));
+    }
+    return sum;
+}
+
+// Objects the FP32 bound could not certify, one per wave.  The wave walks the
+// object again in FP32 (the same code, so the tile holds the scores the walk
+// had).  A cluster j is a candidate unless the bound proves it below the
+// FP32 winner: every non-candidate's FP64 score is then strictly smaller than
+// the winner's, so the FP64 argmax (lowest j on equal scores) is among the
+// candidates.  Candidates get their exact FP64 score and, in ascending j with
+// a strict test from 0, the reference's rule picks the cluster.
+template <int VT>
+__global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
+    extern __shared__ float4 lds4[];
+    const WalkArgs& w = a.w;
     const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    float* tile = reinterpret_cast<float*>(lds4) + (int64_t)wv * w.tile_stride;
+    zero_tile(tile, w.tile_stride, lane);
     const int64_t nq = (int64_t)a.cnt->n_rescore;
-    for (int64_t w = blockIdx.x; w < nq; w += gridDim.x) {
-        const int64_t i = a.rescore_list[w];
-        const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
+    for (int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; q < nq; q += nwaves) {
+        const int64_t i = a.rescore_list[q];
+        const int64_t hb = w.x_ptr[i], he = w.x_ptr[i + 1];
         const int32_t prev = a.prev[i];
+        const int32_t fw = a.best_id[i];
+        double c, ab, g;
+        cert_consts(a.valtype, he - hb, &c, &ab, &g);
+        const double thr = cert_lb((double)a.best[i], c, ab, g);
         double best = 0.0;
         int32_t bj = prev;
-        double rho_fp32_winner = -1.0;
-        const int32_t fp32_winner = a.best_id[i];
-        for (int r = 0; r < a.R64; ++r) {
-            const int32_t base = r * a.k_r64;
-            const int32_t kr = min(a.k_r64, a.k - base);
-            for (int s = lane; s < kr; s += kWave) t64[s] = 0.0;
-            for (int64_t h0 = hb; h0 < he; h0 += kWave) {
-                const int cnt = (int)min((int64_t)kWave, he - h0);
-                double v = 0.0;
-                int64_t lo = 0, hi = 0;
-                if (lane < cnt) {
-                    const int32_t t = a.x_idx[h0 + lane];
-                    v = (double)a.x_val[h0 + lane];
-                    const int64_t pb = a.ivf_ptr[t], pe = a.ivf_ptr[t + 1];
-                    // first entry with cluster >= base, then first >= base + kr
-                    int64_t l = pb, u = pe;
-                    while (l < u) {
-                        const int64_t mid = (l + u) >> 1;
-                        if (a.cid[mid] < base) l = mid + 1; else u = mid;
-                    }
-                    lo = l;
-                    u = pe;
-                    while (l < u) {
-                        const int64_t mid = (l + u) >> 1;
-                        if (a.cid[mid] < base + kr) l = mid + 1; else u = mid;
-                    }
-                    hi = l;
+        double rho_fw = -1.0;   // FP64 score of the FP32 winner (always a candidate)
+        for (int r = 0; r < w.R; ++r) {
+            const int32_t base = r * w.k_r;
+            const int32_t kr = min(w.k_r, w.k - base);
+            accumulate_object<VT>(w, i, r, base, kr, tile, lane);
+            for (int s0 = 0; s0 < kr; s0 += 4 * kWave) {
+                const int s = s0 + 4 * lane;
+                float4 q4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (s < kr) {
+                    q4 = *reinterpret_cast<const float4*>(tile + s);
+                    *reinterpret_cast<float4*>(tile + s) = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
-                for (int hh = 0; hh < cnt; ++hh) {
-                    const int64_t qb = rl64(lo, hh), qe = rl64(hi, hh);
-                    const double vv = __longlong_as_double(rl64(__double_as_longlong(v), hh));
-                    for (int64_t q = qb + lane; q < qe; q += kWave) {
-                        const int32_t j = a.cid[q] - base;
-                        const double p = vv * a.val64[q];
-                        t64[j] = t64[j] + p;
-                    }
-                }
-            }
-            // argmax of the range: larger value, lowest cluster on equal values
-            double rb = 0.0;
-            int32_t rj = -1;
-            for (int s = lane; s < kr; s += kWave) {
-                const double x = t64[s];
-                if (x > rb) { rb = x; rj = s; }
-                if (base + s == fp32_winner) rho_fp32_winner = x;
-            }
+                const float x[4] = {q4.x, q4.y, q4.z, q4.w};
+                uint64_t mk[4];
 #pragma unroll
-            for (int o = kWave / 2; o >= 1; o >>= 1) {
-                const double ob = __shfl_xor(rb, o, kWave);
-                const int32_t oj = __shfl_xor(rj, o, kWave);
-                if (ob > rb || (ob == rb && oj >= 0 && (rj < 0 || oj < rj))) { rb = ob; rj = oj; }
-                const double ow = __shfl_xor(rho_fp32_winner, o, kWave);
-                rho_fp32_winner = fmax(rho_fp32_winner, ow);
-            }
-            // ranges in ascending order with a strict test: earlier ranges keep ties
-            if (rb > best) {
-                best = rb;
-                bj = base + rj;
+                for (int u = 0; u < 4; ++u)
+                    mk[u] = __ballot(s + u < kr && cert_ub((double)x[u], c, ab, g) >= thr);
+                uint64_t any = mk[0] | mk[1] | mk[2] | mk[3];
+                while (any) {   // uniform: ascending lanes, then the lane's 4 slots
+                    const int l = __builtin_ctzll(any);
+                    any &= any - 1;
+                    for (int u = 0; u < 4; ++u) {
+                        if (!((mk[u] >> l) & 1ull)) continue;
+                        const int32_t j = base + s0 + 4 * l + u;
+                        const double e = exact_score(a, hb, he, j, lane);
+                        if (e > best) {
+                            best = e;
+                            bj = j;
+                        }
+                        if (j == fw) rho_fw = e;
+                    }
+                }
             }
         }
-        // best, bj and rho_fp32_winner are wave-uniform: identical stores from
-        // every lane, and an idempotent max
+        // best, bj and rho_fw are wave-uniform: identical stores from every
+        // lane, and an idempotent max
         a.assign[i] = best > 0.0 ? bj : prev;
         a.rho[i] = best;
-        if (rho_fp32_winner > 0.0) {
-            const double e = fabs((double)a.best[i] - rho_fp32_winner) / rho_fp32_winner;
+        if (rho_fw > 0.0) {
+            const double e = fabs((double)a.best[i] - rho_fw) / rho_fw;
             atomicMax(&a.cnt->max_err_bits, (unsigned long long)__double_as_longlong(e));
         }
     }
@@ -567,8 +595,18 @@ hipError_t walk_set_lds_limit(int lds_bytes) {
             hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
         if (e != hipSuccess) return e;
     }
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 8 * 8192);
+    for (int vt = IVF_VAL_F32; vt <= IVF_VAL_F16; ++vt) {
+        hipError_t e = hipFuncSetAttribute(rescore_kernel_ptr(vt),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+const void* rescore_kernel_ptr(int valtype) {
+    if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_rescore<IVF_VAL_F32>);
+    if (valtype == IVF_VAL_BF16) return reinterpret_cast<const void*>(&k_rescore<IVF_VAL_BF16>);
+    return reinterpret_cast<const void*>(&k_rescore<IVF_VAL_F16>);
 }
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
@@ -577,8 +615,15 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rescore(const RescoreArgs& a, int grid, hipStream_t s) {
-    k_rescore<<<grid, kWave, (size_t)a.k_r64 * 8, s>>>(a);
+hipError_t launch_rescore(const RescoreArgs& a, int waves, int grid, hipStream_t s) {
+    const dim3 blk(kWave * waves);
+    const size_t lds = (size_t)waves * a.w.tile_stride * 4;
+    if (a.valtype == IVF_VAL_F32)
+        k_rescore<IVF_VAL_F32><<<grid, blk, lds, s>>>(a);
+    else if (a.valtype == IVF_VAL_BF16)
+        k_rescore<IVF_VAL_BF16><<<grid, blk, lds, s>>>(a);
+    else
+        k_rescore<IVF_VAL_F16><<<grid, blk, lds, s>>>(a);
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ struct Plan {
     int32_t waves = 0;        // waves per workgroup, each owning one tile
     int32_t chunk = 0;        // objects per work-queue item
     int32_t tile_stride = 0;  // floats per tile (k_r rounded up to a multiple of 4)
-    int32_t k_r64 = 0;        // clusters per FP64 re-score tile
+    int32_t k_r64 = 0;        // clusters per range of the FP64 re-score (its FP32 candidate walk)
     int32_t R64 = 0;
     int32_t lds_bytes = 0;    // per workgroup of the walk
 };
@@ -123,6 +123,10 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                             uint32_t* vals_alt, int64_t n, int bits, void* tmp, hipStream_t s,
                             const uint32_t* vals_in_first = nullptr,
                             const int64_t* n_dev = nullptr);
+// The same with 8-byte values (the whole payload moves with its key).
+hipError_t radix_sort_pairs_u64(uint32_t* keys, uint2* vals, uint32_t* keys_alt, uint2* vals_alt,
+                                int64_t n, int bits, void* tmp, hipStream_t s,
+                                const uint2* vals_in_first = nullptr);
 
 // Plan of the walk for k clusters.
 ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err);

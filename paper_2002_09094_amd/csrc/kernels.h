@@ -37,13 +37,11 @@ struct MergeArgs {
 };
 
 struct RescoreArgs {
-    const int64_t* x_ptr;
-    const int32_t* x_idx;
-    const float* x_val;
-    const int64_t* ivf_ptr;   // [d + 1]
-    const int32_t* cid;       // [nnzM] cluster of every inverted-file entry
-    const double* val64;      // [nnzM] FP64 mean value of every entry
-    int32_t k, k_r64, R64;
+    WalkArgs w;               // the walk's view of the objects and the inverted file
+    const int64_t* mm_ptr;    // [k + 1] the walk's means, mean-major FP64
+    const int32_t* mm_idx;
+    const double* mm_val;
+    int32_t valtype;
     const int32_t* rescore_list;
     const int32_t* prev;
     int32_t* assign;
@@ -65,7 +63,10 @@ hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int3
 hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes, int grid,
                        hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
-hipError_t launch_rescore(const RescoreArgs& a, int grid, hipStream_t s);
+// FP64 re-score of the queued objects: `waves` waves per workgroup, each with
+// its own tile of w.tile_stride floats.
+hipError_t launch_rescore(const RescoreArgs& a, int waves, int grid, hipStream_t s);
+const void* rescore_kernel_ptr(int valtype);
 hipError_t launch_objective(const double* rho, const int32_t* assign, const int32_t* prev,
                             int64_t n, double* part, int nblocks, double* out, Counters* cnt,
                             hipStream_t s);
@@ -88,10 +89,11 @@ hipError_t launch_validate_means(const int64_t* ptr, const int32_t* idx, const d
 hipError_t launch_row_ids(const int64_t* ptr, int64_t n, int32_t* rowid, hipStream_t s);
 hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s);
 hipError_t launch_copy_keys(const int32_t* in, uint32_t* out, int64_t n, hipStream_t s);
-// After sorting (term, position): term-major view of the objects.
+// After sorting (term, position): term-major view of the objects, the object
+// of every entry and its (term, FP32 value bits).
 hipError_t launch_build_xt(const uint32_t* sorted_terms, const uint32_t* sorted_pos,
                            const int32_t* rowid, const float* x_val, int64_t nnz,
-                           int32_t* xt_obj, int32_t* xt_term, float* xt_val, hipStream_t s);
+                           int32_t* xt_obj, uint2* xt_tv, hipStream_t s);
 // Per-term fixed-point scale: every member sum of term t is exact in units of
 // 2^shift[t] unless the term's values span too wide a range (then rounded).
 hipError_t launch_term_shift(const int32_t* x_idx, const float* x_val, int64_t nnz, int64_t d,
@@ -108,15 +110,12 @@ struct UpdateArgs {
     int32_t k;
     const int32_t* assign;
     const int32_t* xt_obj;
-    const int32_t* xt_term;
-    const float* xt_val;
+    const uint2* xt_tv;     // (term, FP32 value bits) per term-major entry
     const int16_t* shift;
     // sort buffers (nnz)
     uint32_t* keys;
-    uint32_t* vals;
     uint32_t* keys_alt;
-    uint32_t* vals_alt;
-    const uint32_t* iota;
+    uint2* pay;             // (term, value) of the entries in cluster order
     // segments (nnz capacity)
     uint32_t* flag;
     uint32_t* segpos;
@@ -173,7 +172,6 @@ struct IvfArgs {
     int64_t* dsz;        // [d * R + 1] dense slab sizes, then their offsets (scanned)
     void* slab;          // dense slabs (sized by the first phase)
     int32_t* cid;        // [nnzM]
-    double* val64;       // [nnzM]
     void* post;          // [nnzM] uint2 or uint32
     void* tmp;
 };

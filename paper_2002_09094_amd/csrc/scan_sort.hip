@@ -135,10 +135,11 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
 }
 
 // Stable scatter: items are ranked in their input order (round, wave, lane).
+template <typename V>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
-    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n,
+    const uint32_t* __restrict__ keys, const V* __restrict__ vals, int64_t n,
     const int64_t* n_dev, int shift, const uint32_t* __restrict__ offs, int64_t nt,
-    uint32_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
+    uint32_t* __restrict__ okeys, V* __restrict__ ovals) {
     constexpr int W = kBlock / kWave;
     n = bounded_count(n, n_dev);
     __shared__ uint32_t run[kDigits];
@@ -151,7 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         const int64_t i = base + (int64_t)r * kBlock + tid;
         const bool valid = i < n;
         uint32_t key = valid ? keys[i] : 0u;
-        uint32_t val = valid ? vals[i] : 0u;
+        V val{};
+        if (valid) val = vals[i];
         const uint32_t d = (key >> shift) & (kDigits - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -188,8 +190,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
 
 // The result of an odd number of passes copied back (a kernel, so the sort
 // records no memory-copy node of host-chosen size when captured in a graph).
-__global__ void k_copy2(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b,
-                        uint32_t* __restrict__ oa, uint32_t* __restrict__ ob, int64_t n,
+template <typename V>
+__global__ void k_copy2(const uint32_t* __restrict__ a, const V* __restrict__ b,
+                        uint32_t* __restrict__ oa, V* __restrict__ ob, int64_t n,
                         const int64_t* n_dev) {
     n = bounded_count(n, n_dev);
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -197,6 +200,40 @@ __global__ void k_copy2(const uint32_t* __restrict__ a, const uint32_t* __restri
         oa[i] = a[i];
         ob[i] = b[i];
     }
+}
+
+template <typename V>
+hipError_t radix_sort_impl(uint32_t* keys, V* vals, uint32_t* keys_alt, V* vals_alt, int64_t n,
+                           int bits, void* tmp, hipStream_t s, const V* vals_in_first,
+                           const int64_t* n_dev) {
+    if (n <= 0) return hipSuccess;
+    if (bits < 1) bits = 1;
+    const int64_t nt = ntiles(n);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(tmp);
+    void* stmp = reinterpret_cast<char*>(tmp) +
+                 (((size_t)nt * kDigits * sizeof(uint32_t) + 255) & ~(size_t)255);
+    const int passes = (bits + 7) / 8;
+    uint32_t *ki = keys, *ko = keys_alt;
+    V *vi = vals, *vo = vals_alt;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        const V* vin = (p == 0 && vals_in_first) ? vals_in_first : vi;
+        k_radix_hist<<<(unsigned)nt, kBlock, 0, s>>>(ki, n, n_dev, shift, hist, nt);
+        hipError_t e = scan_impl<uint32_t>(hist, hist, nt * kDigits, stmp, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<V><<<(unsigned)nt, kBlock, 0, s>>>(ki, vin, n, n_dev, shift, hist, nt, ko,
+                                                          vo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint32_t* t = ki; ki = ko; ko = t;
+        V* tv = vi; vi = vo; vo = tv;
+    }
+    if (ki != keys) {   // odd number of passes: move the result home
+        k_copy2<V><<<(unsigned)std::min<int64_t>(nt * kItems, 65536), kBlock, 0, s>>>(
+            ki, vi, keys, vals, n, n_dev);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -222,32 +259,15 @@ size_t radix_tmp_bytes(int64_t n) {
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
                             uint32_t* vals_alt, int64_t n, int bits, void* tmp, hipStream_t s,
                             const uint32_t* vals_in_first, const int64_t* n_dev) {
-    if (n <= 0) return hipSuccess;
-    if (bits < 1) bits = 1;
-    const int64_t nt = ntiles(n);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(tmp);
-    void* stmp = reinterpret_cast<char*>(tmp) +
-                 (((size_t)nt * kDigits * sizeof(uint32_t) + 255) & ~(size_t)255);
-    const int passes = (bits + 7) / 8;
-    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-    for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        const uint32_t* vin = (p == 0 && vals_in_first) ? vals_in_first : vi;
-        k_radix_hist<<<(unsigned)nt, kBlock, 0, s>>>(ki, n, n_dev, shift, hist, nt);
-        hipError_t e = scan_impl<uint32_t>(hist, hist, nt * kDigits, stmp, s);
-        if (e != hipSuccess) return e;
-        k_radix_scatter<<<(unsigned)nt, kBlock, 0, s>>>(ki, vin, n, n_dev, shift, hist, nt, ko, vo);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        uint32_t* t = ki; ki = ko; ko = t;
-        t = vi; vi = vo; vo = t;
-    }
-    if (ki != keys) {   // odd number of passes: move the result home
-        k_copy2<<<(unsigned)std::min<int64_t>(nt * kItems, 65536), kBlock, 0, s>>>(
-            ki, vi, keys, vals, n, n_dev);
-        return hipGetLastError();
-    }
-    return hipSuccess;
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s,
+                                     vals_in_first, n_dev);
+}
+
+hipError_t radix_sort_pairs_u64(uint32_t* keys, uint2* vals, uint32_t* keys_alt, uint2* vals_alt,
+                                int64_t n, int bits, void* tmp, hipStream_t s,
+                                const uint2* vals_in_first) {
+    return radix_sort_impl<uint2>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s, vals_in_first,
+                                  nullptr);
 }
 
 }  // namespace ivf

@@ -99,14 +99,12 @@ __global__ void k_copy_keys(const int32_t* in, uint32_t* out, int64_t n,
 }
 
 __global__ void k_build_xt(const uint32_t* st, const uint32_t* sp, const int32_t* rowid,
-                           const float* x_val, int64_t nnz, int32_t* xt_obj, int32_t* xt_term,
-                           float* xt_val) {
+                           const float* x_val, int64_t nnz, int32_t* xt_obj, uint2* xt_tv) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
          q += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t e = sp[q];
-        xt_term[q] = (int32_t)st[q];
         xt_obj[q] = rowid[e];
-        xt_val[q] = x_val[e];
+        xt_tv[q] = make_uint2(st[q], __float_as_uint(x_val[e]));
     }
 }
 
@@ -179,9 +177,10 @@ __global__ void k_zero_i64(int64_t* p, int64_t n) {
         p[i] = 0;
 }
 
-__global__ void k_seg_flags(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                            const int32_t* __restrict__ xt_term, int64_t nnz, int32_t k,
-                            uint32_t* __restrict__ flag, int64_t* scal) {
+// Entries sorted by cluster carry their (term, value) payload, so runs of
+// equal (cluster, term) are found by reading neighbours, not by gathers.
+__global__ void k_seg_flags(const uint32_t* __restrict__ keys, const uint2* __restrict__ pay,
+                            int64_t nnz, int32_t k, uint32_t* __restrict__ flag, int64_t* scal) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
          q += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t key = keys[q];
@@ -191,7 +190,7 @@ __global__ void k_seg_flags(const uint32_t* __restrict__ keys, const uint32_t* _
             if (q == 0) f = 1;
             else {
                 const uint32_t kp = keys[q - 1];
-                f = (kp != key || xt_term[vals[q]] != xt_term[vals[q - 1]]) ? 1u : 0u;
+                f = (kp != key || pay[q].x != pay[q - 1].x) ? 1u : 0u;
             }
             if (q == nnz - 1 || keys[q + 1] >= (uint32_t)k) scal[0] = q + 1;
         }
@@ -219,11 +218,10 @@ __device__ inline unsigned long long to_fixed(float v, int sh) {
 
 constexpr int kRun = 8;
 
-__global__ void k_seg_sums(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+__global__ void k_seg_sums(const uint32_t* __restrict__ keys, const uint2* __restrict__ pay,
                            const uint32_t* __restrict__ flag,
                            const uint32_t* __restrict__ segpos,
-                           const int32_t* __restrict__ xt_term,
-                           const float* __restrict__ xt_val, const int16_t* __restrict__ shift,
+                           const int16_t* __restrict__ shift,
                            const int64_t* scal, unsigned long long* __restrict__ acc,
                            int32_t* __restrict__ seg_j, int32_t* __restrict__ seg_t) {
     const int64_t nv = scal[0];
@@ -233,8 +231,8 @@ __global__ void k_seg_sums(const uint32_t* __restrict__ keys, const uint32_t* __
     int64_t cur = -1;
     unsigned long long run = 0;
     for (int64_t q = q0; q < q1; ++q) {
-        const uint32_t e = vals[q];
-        const int32_t t = xt_term[e];
+        const uint2 tv = pay[q];
+        const int32_t t = (int32_t)tv.x;
         const int64_t s = (int64_t)segpos[q] + flag[q] - 1;
         if (flag[q]) {
             seg_j[s] = (int32_t)keys[q];
@@ -245,7 +243,7 @@ __global__ void k_seg_sums(const uint32_t* __restrict__ keys, const uint32_t* __
             cur = s;
             run = 0;
         }
-        run += to_fixed(xt_val[e], shift[t]);
+        run += to_fixed(__uint_as_float(tv.y), shift[t]);
     }
     if (cur >= 0) atomicAdd(&acc[cur], run);
 }
@@ -405,7 +403,7 @@ __device__ inline uint32_t bf16_rne(float f) {
 __global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __restrict__ mm_row,
                            const double* __restrict__ mm_val, int64_t nnzM, const int64_t* n_dev,
                            int32_t k_r, int valtype, int32_t* __restrict__ cid,
-                           double* __restrict__ val64, void* __restrict__ post) {
+                           void* __restrict__ post) {
     nnzM = bounded_count(nnzM, n_dev);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -413,7 +411,6 @@ __global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __r
         const int32_t j = mm_row[p];
         const double u = mm_val[p];
         cid[q] = j;
-        val64[q] = u;
         const float f = (float)u;
         if (valtype == IVF_VAL_F32) {
             reinterpret_cast<uint2*>(post)[q] = make_uint2((uint32_t)j, __float_as_uint(f));
@@ -565,10 +562,9 @@ hipError_t launch_copy_keys(const int32_t* in, uint32_t* out, int64_t n, hipStre
 }
 
 hipError_t launch_build_xt(const uint32_t* st, const uint32_t* sp, const int32_t* rowid,
-                           const float* x_val, int64_t nnz, int32_t* xt_obj, int32_t* xt_term,
-                           float* xt_val, hipStream_t s) {
-    k_build_xt<<<capped(nnz), kThreads, 0, s>>>(st, sp, rowid, x_val, nnz, xt_obj, xt_term,
-                                                 xt_val);
+                           const float* x_val, int64_t nnz, int32_t* xt_obj, uint2* xt_tv,
+                           hipStream_t s) {
+    k_build_xt<<<capped(nnz), kThreads, 0, s>>>(st, sp, rowid, x_val, nnz, xt_obj, xt_tv);
     return hipGetLastError();
 }
 
@@ -590,17 +586,20 @@ hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s) {
     if (nnz > 0) {
         k_keys<<<capped(nnz), kThreads, 0, s>>>(a.xt_obj, a.assign, nnz, a.k, a.keys);
         HIP_RET(hipGetLastError());
-        HIP_RET(radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, nnz, bits_for(a.k),
-                                 a.tmp, s, a.iota));
-        k_seg_flags<<<capped(nnz), kThreads, 0, s>>>(a.keys, a.vals, a.xt_term, nnz, a.k, a.flag,
-                                                     a.scal);
+        // stable sort by cluster; the (term, value) payload moves with its key.
+        // The segment-sum buffer (8 B per entry, written only after the sort)
+        // is the payload's second buffer.
+        HIP_RET(radix_sort_pairs_u64(a.keys, a.pay, a.keys_alt,
+                                     reinterpret_cast<uint2*>(a.seg_acc), nnz, bits_for(a.k),
+                                     a.tmp, s, a.xt_tv));
+        k_seg_flags<<<capped(nnz), kThreads, 0, s>>>(a.keys, a.pay, nnz, a.k, a.flag, a.scal);
         HIP_RET(hipGetLastError());
         HIP_RET(exclusive_scan_u32(a.flag, a.segpos, nnz, a.tmp, s));
         k_seg_count<<<1, 64, 0, s>>>(a.flag, a.segpos, nnz, a.scal);
         k_zero_segs<<<capped(nnz), kThreads, 0, s>>>(a.seg_acc, a.scal, nnz);
-        k_seg_sums<<<grid_for(nnz, kRun), kThreads, 0, s>>>(a.keys, a.vals, a.flag, a.segpos,
-                                                            a.xt_term, a.xt_val, a.shift, a.scal,
-                                                            a.seg_acc, a.seg_j, a.seg_t);
+        k_seg_sums<<<grid_for(nnz, kRun), kThreads, 0, s>>>(a.keys, a.pay, a.flag, a.segpos,
+                                                            a.shift, a.scal, a.seg_acc, a.seg_j,
+                                                            a.seg_t);
         HIP_RET(hipGetLastError());
     }
     k_cstart<<<grid_for(a.k + 1), kThreads, 0, s>>>(a.seg_j, a.scal, a.k, a.cstart);
@@ -643,7 +642,7 @@ hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
                                  a.nnz_dev));
         k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM,
                                                        a.nnz_dev, a.k_r, a.valtype, a.cid,
-                                                       a.val64, a.post);
+                                                       a.post);
         HIP_RET(hipGetLastError());
     }
     k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.nnz_dev, a.d, a.ivf_ptr);

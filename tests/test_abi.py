@@ -48,7 +48,7 @@ def test_planner():
     assert p["ranges"] * p["k_r"] >= 10_000 and p["k_r"] <= 1280 and p["waves"] == 8
     assert p["lds_bytes"] <= 160 * 1024
     p = ivf.plan_shape(50_000)
-    assert p["ranges"] >= 40 and p["ranges64"] == 7
+    assert p["ranges"] >= 40 and p["rescore_ranges"] == p["ranges"] and p["rescore_k_r"] == p["k_r"]
     p = ivf.plan_shape(1000, cluster_range=64)
     assert p["k_r"] <= 64 and p["ranges"] == 16
     with pytest.raises(ivf.IvfError):

@@ -121,11 +121,38 @@ template <> struct Slab<IVF_VAL_F16> : Slab16<IVF_VAL_F16> {};
 
 constexpr int kDenseUnroll = 4;
 
+// A slab of at most kDenseOne * 64 groups (ranges up to 1,280 clusters) is
+// walked with every global load in flight at once, then one 128-bit LDS
+// read-modify-write per group: a single memory round trip per term.
+constexpr int kDenseOne = 5;
+
 template <int VT>
 __device__ inline void walk_dense(const typename Slab<VT>::T* __restrict__ S, int32_t kr4, float v,
                                   float* tile, int lane) {
     using D = Slab<VT>;
     float4* t4 = reinterpret_cast<float4*>(tile);
+    if (kr4 <= kDenseOne * kWave) {
+        typename D::T x[kDenseOne];
+#pragma unroll
+        for (int u = 0; u < kDenseOne; ++u) {
+            const int32_t g = u * kWave + lane;
+            if (g < kr4) x[u] = S[g];
+        }
+#pragma unroll
+        for (int u = 0; u < kDenseOne; ++u) {
+            const int32_t g = u * kWave + lane;
+            if (g < kr4) {
+                const float4 m = D::widen(x[u]);
+                float4 o = t4[g];
+                o.x = o.x + v * m.x;
+                o.y = o.y + v * m.y;
+                o.z = o.z + v * m.z;
+                o.w = o.w + v * m.w;
+                t4[g] = o;
+            }
+        }
+        return;
+    }
     int32_t g0 = 0;   // groups of 4 slots; kr4 groups in the slab
     for (; g0 + kDenseUnroll * kWave <= kr4; g0 += kDenseUnroll * kWave) {
         typename D::T x[kDenseUnroll];

@@ -56,12 +56,34 @@ template <> struct Entry<IVF_VAL_F16> : Entry16<IVF_VAL_F16> {};
 
 constexpr int kUnroll = 8;
 
+// Posting-entry loads.  NT marks them non-temporal: sparse slices (tail
+// terms) are rarely re-read soon, so they should not evict the head terms'
+// dense slabs from L2.  That measured 2.7 % faster for the FP32 walk at 8M
+// documents and 5 % slower for 16-bit values, whose smaller working set does
+// reuse its sparse slices; it is used for the FP32 single-instance walk only.
+template <bool NT>
+__device__ inline uint2 load_entry(const uint2* p) {
+    if constexpr (NT) {
+        uint2 r;
+        r.x = __builtin_nontemporal_load(&p->x);
+        r.y = __builtin_nontemporal_load(&p->y);
+        return r;
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ inline uint32_t load_entry(const uint32_t* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // One term's posting slice [qb, qe) accumulated into the wave's own tile:
 // tile[c] = tile[c] + v * u for every entry (c, u).  LDS float atomics are
 // slow on this part and not needed: the tile belongs to this wave alone, and
 // one term's list names every cluster at most once, so all reads of a batch
 // may be issued before its writes.  Slots are updated in ascending term order.
-template <int VT>
+template <int VT, bool NT>
 __device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, int64_t qb,
                                   int64_t qe, float v, float* tile, int32_t base, int lane) {
     using E = Entry<VT>;
@@ -69,7 +91,7 @@ __device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, i
     for (; q0 + kUnroll * kWave <= qe; q0 += kUnroll * kWave) {
         typename E::T e[kUnroll];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) e[u] = P[q0 + u * kWave + lane];
+        for (int u = 0; u < kUnroll; ++u) e[u] = load_entry<NT>(P + q0 + u * kWave + lane);
         float r[kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) r[u] = tile[E::slot(e[u], base)];
@@ -86,7 +108,7 @@ __device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, i
         for (int u = 0; u < kUnroll; ++u) {
             const int64_t q = q0 + u * kWave + lane;
             ok[u] = q < qe;
-            if (ok[u]) e[u] = P[q];
+            if (ok[u]) e[u] = load_entry<NT>(P + q);
         }
         float r[kUnroll];
 #pragma unroll
@@ -200,7 +222,7 @@ __device__ inline void top2_combine(float& b, int32_t& id, float& s, float ob, i
 // Object i's FP32 scores against cluster range r (clusters base .. base + kr)
 // accumulated into the wave's tile, its terms in ascending order.  Returns
 // the posting entries walked (the object's share of M in this range).
-template <int VT>
+template <int VT, bool NT = false>
 __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r, int32_t base,
                                             int32_t kr, float* tile, int lane) {
     const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
@@ -221,8 +243,8 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
             const float vv = rlf(v, hh);
             m += (int32_t)cn;
             if (p >= 0)
-                walk_slice<VT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p, p + cn,
-                               vv, tile, base, lane);
+                walk_slice<VT, NT>(reinterpret_cast<const typename Entry<VT>::T*>(a.post), p,
+                                   p + cn, vv, tile, base, lane);
             else
                 walk_dense<VT>(reinterpret_cast<const typename Slab<VT>::T*>(
                                    reinterpret_cast<const char*>(a.slab) +
@@ -235,7 +257,7 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
 
 // One work item: `chunk` consecutive objects against cluster range r, each
 // walked into the wave's tile, its range record written and the tile cleared.
-template <int VT>
+template <int VT, bool NT = false>
 __device__ inline void walk_item(const WalkArgs& a, int64_t w, float* tile, int lane) {
     const int r = (int)(w / a.items_per_range);
     const int64_t c = w - (int64_t)r * a.items_per_range;
@@ -244,7 +266,7 @@ __device__ inline void walk_item(const WalkArgs& a, int64_t w, float* tile, int 
     const int64_t i0 = c * a.chunk;
     const int64_t i1 = min(a.n, i0 + a.chunk);
     for (int64_t i = i0; i < i1; ++i) {
-        const int32_t m = accumulate_object<VT>(a, i, r, base, kr, tile, lane);
+        const int32_t m = accumulate_object<VT, NT>(a, i, r, base, kr, tile, lane);
         // fused top-2 over the tile, clearing it for the next object
         float b = 0.f, s2 = 0.f;
         int32_t id = -1;
@@ -319,7 +341,7 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(W
         for (;;) {
             const int64_t w = claim_item(&a.cnt->work, lane);
             if (w >= total) break;
-            walk_item<VT>(a, w, tile, lane);
+            walk_item<VT, true>(a, w, tile, lane);
         }
     } else {
         // static round robin: at 8 waves per SIMD the claim would spill

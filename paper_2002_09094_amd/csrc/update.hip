@@ -218,34 +218,88 @@ __device__ inline unsigned long long to_fixed(float v, int sh) {
 
 constexpr int kRun = 8;
 
-__global__ void k_seg_sums(const uint32_t* __restrict__ keys, const uint2* __restrict__ pay,
-                           const uint32_t* __restrict__ flag,
-                           const uint32_t* __restrict__ segpos,
-                           const int16_t* __restrict__ shift,
-                           const int64_t* scal, unsigned long long* __restrict__ acc,
-                           int32_t* __restrict__ seg_j, int32_t* __restrict__ seg_t) {
+__device__ inline unsigned long long shfl_up_u64(unsigned long long x, int d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, kWave);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, kWave);
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ inline int64_t shfl_up_i64(int64_t x, int d) {
+    return (int64_t)shfl_up_u64((unsigned long long)x, d);
+}
+__device__ inline int64_t shfl_down_i64(int64_t x, int d) {
+    const uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)x, d, kWave);
+    const uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)(x >> 32), d, kWave);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int64_t readlane_i64(int64_t x, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Fixed-point sums of the (cluster, term) segments.  One wave takes 64 * kRun
+// consecutive entries (in cluster order) as kRun chunks of 64; within a chunk
+// an inclusive segmented scan over the lanes (segments are contiguous) sums
+// each run, and the lane that ends a run adds it to the segment's
+// accumulator.  A run reaching the chunk's last lane is carried into the next
+// chunk, so a long segment costs one atomic per wave, not one per lane.  The
+// sums are integers: exact and independent of the order of the additions.
+__global__ __launch_bounds__(kThreads) void k_seg_sums(const uint32_t* __restrict__ keys,
+                                                       const uint2* __restrict__ pay,
+                                                       const uint32_t* __restrict__ flag,
+                                                       const uint32_t* __restrict__ segpos,
+                                                       const int16_t* __restrict__ shift,
+                                                       const int64_t* scal,
+                                                       unsigned long long* __restrict__ acc,
+                                                       int32_t* __restrict__ seg_j,
+                                                       int32_t* __restrict__ seg_t) {
     const int64_t nv = scal[0];
-    const int64_t q0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * kRun;
-    if (q0 >= nv) return;
-    const int64_t q1 = min(nv, q0 + kRun);
-    int64_t cur = -1;
-    unsigned long long run = 0;
-    for (int64_t q = q0; q < q1; ++q) {
-        const uint2 tv = pay[q];
-        const int32_t t = (int32_t)tv.x;
-        const int64_t s = (int64_t)segpos[q] + flag[q] - 1;
-        if (flag[q]) {
-            seg_j[s] = (int32_t)keys[q];
-            seg_t[s] = t;
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t qbase = wave * ((int64_t)kWave * kRun);
+    if (qbase >= nv) return;   // the same for all lanes of the wave
+    int64_t carry_seg = -1;    // wave-uniform
+    unsigned long long carry = 0;
+    for (int u = 0; u < kRun; ++u) {
+        const int64_t q = qbase + (int64_t)u * kWave + lane;
+        const bool valid = q < nv;
+        int64_t sg = -1;
+        unsigned long long v = 0;
+        if (valid) {
+            const uint2 tv = pay[q];
+            const int32_t t = (int32_t)tv.x;
+            sg = (int64_t)segpos[q] + flag[q] - 1;
+            if (flag[q]) {
+                seg_j[sg] = (int32_t)keys[q];
+                seg_t[sg] = t;
+            }
+            v = to_fixed(__uint_as_float(tv.y), shift[t]);
         }
-        if (s != cur) {
-            if (cur >= 0) atomicAdd(&acc[cur], run);
-            cur = s;
-            run = 0;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const unsigned long long ov = shfl_up_u64(v, d);
+            const int64_t os = shfl_up_i64(sg, d);
+            if (lane >= d && os == sg) v += ov;
         }
-        run += to_fixed(__uint_as_float(tv.y), shift[t]);
+        const int64_t first = readlane_i64(sg, 0);
+        if (carry_seg >= 0 && first != carry_seg) {   // the carried run ended with the last chunk
+            if (lane == 0) atomicAdd(&acc[carry_seg], carry);
+            carry_seg = -1;
+            carry = 0;
+        }
+        if (carry_seg >= 0 && sg == carry_seg) v += carry;
+        const int64_t next = shfl_down_i64(sg, 1);
+        if (valid && lane < kWave - 1 && next != sg) atomicAdd(&acc[sg], v);
+        const int64_t last = readlane_i64(sg, kWave - 1);
+        if (last >= 0) {   // the last lane's run may continue into the next chunk
+            carry_seg = last;
+            carry = (unsigned long long)readlane_i64((int64_t)v, kWave - 1);
+        } else {
+            carry_seg = -1;
+            carry = 0;
+        }
     }
-    if (cur >= 0) atomicAdd(&acc[cur], run);
+    if (carry_seg >= 0 && lane == 0) atomicAdd(&acc[carry_seg], carry);
 }
 
 __device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t lo, int64_t hi, int32_t x) {

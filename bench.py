@@ -215,6 +215,53 @@ def summarize_pmc(out_txt, command, *csvs):
         f.write("\n".join(lines) + "\n")
 
 
+def run_figures(args):
+    """Per-iteration quantities behind the paper's figures on means and
+    multiplications, measured on synthetic data: for several k on 1,000,000
+    documents shaped like the paper's 1M-document PubMed sample (140,000
+    terms, Poisson(60) nonzeros in [3, 1000], Zipf s = 1.1), every Lloyd
+    iteration's distinct terms in the means, their nonzeros sum_j (ntm)_j (the
+    inverted file's size), the mult-adds M of the assignment (Eq. ivf_mult),
+    the changes and the walk time, from the seeded initial state until an
+    assignment changes nothing (at most --steps + 10 iterations)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2002_09094_amd as ivf
+
+    dev = "cuda:0"
+    n, d, seed = 1_000_000, 140_000, 9
+    x = datagen.generate(n, d, 60.0, 3, 1000, 1.1, seed)
+    xd = (torch.from_numpy(x.indptr).to(dev), torch.from_numpy(x.indices).to(dev),
+          torch.from_numpy(x.values).to(dev))
+    log("generated pubmed_1m: n=%d d=%d nnz=%d" % (n, d, x.nnz))
+    out = {"metric": "per-iteration means and mult-adds vs k (synthetic)",
+           "workload": "pubmed_1m", "n": n, "d": d, "lambda": 60.0, "zipf_s": 1.1, "seed": seed,
+           "nnz": x.nnz, "valtype": args.valtype, "runs": []}
+    for k in (1000, 2000, 5000, 10000, 20000):
+        km = ivf.IVFKMeans(*xd, d, k, valtype=args.valtype)
+        km.init_seeds(torch.from_numpy(datagen.seed_objects(x, k, seed).astype(np.int32)).to(dev))
+        a = torch.full((n,), -1, dtype=torch.int32, device=dev)
+        run = {"k": k, "iters": []}
+        for r in range(args.steps + 10):
+            sa = km.assign(a)
+            su = km.update(a)
+            idx = km.get_means()[1]
+            distinct = int(torch.unique(idx).numel())
+            run["iters"].append({"iter": r + 1, "changed": sa["changed"], "mult_adds": sa["mult_adds"],
+                                 "walk_ms": sa["walk_ms"], "nnz_means": su["nnz_means"],
+                                 "distinct_terms": distinct, "objective": su["objective_exact"]})
+            log("k=%d iter %d: changed %d, M %.3e, nnz(means) %d, distinct terms %d, walk %.1f ms"
+                % (k, r + 1, sa["changed"], sa["mult_adds"], su["nnz_means"], distinct,
+                   sa["walk_ms"]))
+            if sa["changed"] == 0:
+                break
+        km.close()
+        out["runs"].append(run)
+    print(json.dumps(out), flush=True)
+
+
 BATCH_METRIC = "aggregate sparse mult-adds/s, 96 batched instances (uneven N, D, k; restarts)"
 
 
@@ -395,6 +442,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched96":
         run_batched(args)
+        return
+    if args.workload == "figures":
+        run_figures(args)
         return
 
     import numpy as np

@@ -173,6 +173,18 @@ ivf_status ivf_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats);
 ivf_status ivf_iterate(ivf_handle* h, int32_t iters, int32_t* assign, ivf_stats* per_iter);
 
 /*
+ * ivf_converge: Lloyd iterations until an assignment step changes no object's
+ * cluster (the partition, and hence the means, are then a fixed point of the
+ * iteration), or max_iters assignment steps.  The converged step's update is
+ * skipped: it would return the same means.  assign as in ivf_assign;
+ * per_iter (host, [max_iters]) may be NULL; *iters_done receives the number
+ * of assignment steps run (the last has changed == 0 unless max_iters was
+ * reached).  Synchronises.
+ */
+ivf_status ivf_converge(ivf_handle* h, int32_t max_iters, int32_t* assign, ivf_stats* per_iter,
+                        int32_t* iters_done);
+
+/*
  * ivf_get_means: two-call copy of the current means.  With out->indptr NULL
  * only out->k, out->d and out->nnz are filled; otherwise the caller's device
  * buffers (indptr[k+1], indices[nnz], values[nnz], nnz from the first call)

@@ -171,6 +171,17 @@ class IVFKMeans:
         check(_lib.get().ivf_iterate(self._h, int(iters), _ptr(assign), arr), self._h)
         return [arr[i].to_dict() for i in range(int(iters))] if stats else None
 
+    def converge(self, max_iters, assign, stats=True):
+        """Iterate until an assignment step changes nothing (or max_iters steps);
+        returns the per-step stats (the last step's update is skipped)."""
+        import torch
+        _need_cuda(assign, torch.int32, "assign")
+        arr = (_lib.ivf_stats * max(int(max_iters), 1))()
+        done = ctypes.c_int32()
+        check(_lib.get().ivf_converge(self._h, int(max_iters), _ptr(assign), arr,
+                                      ctypes.byref(done)), self._h)
+        return [arr[i].to_dict() for i in range(done.value)]
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.get().ivf_destroy(self._h)

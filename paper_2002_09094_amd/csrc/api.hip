@@ -1114,6 +1114,33 @@ ivf_status ivf_iterate(ivf_handle* h, int32_t iters, int32_t* assign, ivf_stats*
     return IVF_OK;
 }
 
+ivf_status ivf_converge(ivf_handle* h, int32_t max_iters, int32_t* assign, ivf_stats* per_iter,
+                        int32_t* iters_done) {
+    if (!h || !assign || !iters_done || max_iters < 0)
+        return fail(h, IVF_ERR_ARG, "bad argument");
+    *iters_done = 0;
+    for (int32_t r = 0; r < max_iters; ++r) {
+        ivf_stats st{};
+        ivf_status e = ivf_assign(h, assign, &st);
+        if (e != IVF_OK) return e;
+        *iters_done = r + 1;
+        if (st.changed == 0) {
+            // the partition is the previous one, so the update would return
+            // the same means: converged, and the update is skipped
+            st.objective_exact = std::nan("");
+            st.empty_clusters = -1;
+            st.nnz_means = h->nnzM_known ? h->nnzM : -1;
+            st.update_ms = 0.f;
+            if (per_iter) per_iter[r] = st;
+            return IVF_OK;
+        }
+        e = run_update(h, assign, &st);
+        if (e != IVF_OK) return e;
+        if (per_iter) per_iter[r] = st;
+    }
+    return IVF_OK;
+}
+
 ivf_status ivf_get_means(ivf_handle* h, ivf_means* out) {
     if (!h || !out) return fail(h, IVF_ERR_ARG, "null argument");
     if (!h->has_means) return fail(h, IVF_ERR_STATE, "no means yet");

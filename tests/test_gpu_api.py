@@ -154,3 +154,25 @@ def test_batch_multi_iteration_calls_and_tuning_report():
         assert np.array_equal(ba[i].cpu().numpy(), ref[-1].assign.assign)
         assert [s[i]["changed"] for s in stats] == [r.assign.changed for r in ref]
     b.close()
+
+
+def test_converge_stops_at_the_oracle_fixed_point():
+    x, seeds, d, k = _data(seed=408, n=3000, d=2000, k=40)
+    ref = list(oracle.chain(x, seeds, 30))
+    fixed = next(r for r, st in enumerate(ref) if st.assign.changed == 0)   # 0-based step
+    km = ivf.IVFKMeans(*to_dev(x), d, k)
+    km.init_seeds(i32(seeds))
+    a = i32(np.full(x.n, -1, np.int32))
+    stats = km.converge(30, a)
+    assert len(stats) == fixed + 1 and stats[-1]["changed"] == 0
+    assert [s["changed"] for s in stats] == [st.assign.changed for st in ref[:fixed + 1]]
+    assert np.array_equal(a.cpu().numpy(), ref[fixed].assign.assign)
+    gm = means_to_host(*km.get_means(), k, d)
+    assert np.array_equal(gm.indices, ref[fixed - 1].means_out.indices)   # the fixed point's means
+    # a call with a small budget stops there
+    km2 = ivf.IVFKMeans(*to_dev(x), d, k)
+    km2.init_seeds(i32(seeds))
+    a2 = i32(np.full(x.n, -1, np.int32))
+    assert len(km2.converge(2, a2)) == 2
+    km.close()
+    km2.close()

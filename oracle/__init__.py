@@ -7,7 +7,8 @@ It shares no code with the GPU library.
 * ``ivf_oracle.c`` - the naive sparse IVF (Algorithm 3 of the paper: the
   assignment walk over the means' inverted file and the update step), FP64,
   no FMA contraction, OpenMP over objects / clusters with results independent
-  of the thread count.
+  of the thread count; and IVFD's assignment (Algorithm 4: the objects'
+  inverted file queried by each mean in turn).
 * ``dense.py``     - a dense brute-force cosine Lloyd (Algorithm 2 scored with
   Algorithm 3's tie rule), for tiny inputs; bit-identical to the sparse walk.
 * ``exact.py``     - an exact-rational checker (Python ``fractions``).
@@ -47,6 +48,9 @@ def _configure(lib):
     lib.oracle_update.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, i64,
                                   vp, ci]
     lib.oracle_update.restype = i64
+    lib.oracle_ivfd_assign.argtypes = [i64, i64, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                       vp, vp]
+    lib.oracle_ivfd_assign.restype = ci
     lib.oracle_term_counts.argtypes = [i64, i64, vp, vp, i32, vp, vp, vp, vp]
     lib.oracle_term_counts.restype = ci
     return lib
@@ -134,6 +138,29 @@ def assign(x, means: Means, prev: np.ndarray, threads: int = 0) -> AssignResult:
                            _p(prev), _p(out), _p(rho), _p(rho2), _p(stats), _p(mult), threads)
     if rc != 0:
         raise MemoryError("oracle_assign failed")
+    return AssignResult(out, rho, rho2, float(stats[0]), int(stats[1]), int(stats[2]),
+                        int(mult[0]))
+
+
+def ivfd_assign(x, means: Means, prev: np.ndarray) -> AssignResult:
+    """Assignment step of IVFD (Algorithm 4): the objects inverted, each mean a
+    query over them, FP64, single-threaded."""
+    lib = _load()
+    n = x.n
+    xp, xi, xv = _c(x.indptr, np.int64), _c(x.indices, np.int32), _c(x.values, np.float32)
+    mp, mi, mv = _c(means.indptr, np.int64), _c(means.indices, np.int32), _c(means.values,
+                                                                             np.float64)
+    prev = _c(prev, np.int32)
+    out = np.empty(n, np.int32)
+    rho = np.empty(n, np.float64)
+    rho2 = np.empty(n, np.float64)
+    stats = np.zeros(3, np.float64)
+    mult = np.zeros(1, np.int64)
+    rc = lib.oracle_ivfd_assign(n, x.d, _p(xp), _p(xi), _p(xv), means.k, _p(mp), _p(mi),
+                                _p(mv), _p(prev), _p(out), _p(rho), _p(rho2), _p(stats),
+                                _p(mult))
+    if rc != 0:
+        raise MemoryError("oracle_ivfd_assign failed")
     return AssignResult(out, rho, rho2, float(stats[0]), int(stats[1]), int(stats[2]),
                         int(mult[0]))
 

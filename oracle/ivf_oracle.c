@@ -149,6 +149,94 @@ int oracle_assign(int64_t n, int64_t d, const int64_t* xp, const int32_t* xi, co
 }
 
 /*
+ * oracle_ivfd_assign: the assignment step of IVFD (Algorithm 4 of the paper),
+ * which inverts the OBJECTS and queries them with each mean in turn.
+ *
+ * The objects' inverted file holds, for every term s, the list of
+ * (object o, value u) in ascending o.  Means are visited in ascending j.  For
+ * each mean the score vector rho over all N objects starts at zero (reading:
+ * the printed algorithm clears rho once, before the loop over means; scores
+ * of different means must not add up, so it is cleared per mean), then for
+ * every term (s, v') of the mean in ascending s and every (o, u) in the list
+ * of s, rho[o] = rho[o] + v' * u (FP64, separate multiply and add).  After
+ * the mean, every object whose rho exceeds its running rho_max (strictly,
+ * from 0) takes cluster j.  An object never raised above 0 keeps prev.
+ *
+ * For a fixed (object, mean) pair the products are added in ascending term
+ * order, exactly as the means-inverted walk adds them, so every rho and
+ * therefore the partition are bit-identical to oracle_assign's; only the loop
+ * order differs.  rho_2 (largest score of any other cluster) is an extra
+ * output the algorithm does not need.  Arguments as for oracle_assign;
+ * single-threaded.
+ */
+int oracle_ivfd_assign(int64_t n, int64_t d, const int64_t* xp, const int32_t* xi,
+                       const float* xv, int32_t k, const int64_t* mp, const int32_t* mi,
+                       const double* mv, const int32_t* prev, int32_t* out, double* rho_a,
+                       double* rho_2, double* stats, int64_t* mult) {
+    const int64_t nnz = xp[n];
+    int64_t* optr = (int64_t*)calloc((size_t)d + 1, sizeof(int64_t));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(d > 0 ? d : 1));
+    int32_t* oobj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    double* oval = (double*)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double* rho = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* second = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int err = (!optr || !fill || !oobj || !oval || !rho || !second) ? -1 : 0;
+    if (!err) {
+        /* inverted object file: objects in ascending i land in ascending order */
+        for (int64_t e = 0; e < nnz; ++e) optr[xi[e] + 1] += 1;
+        for (int64_t t = 0; t < d; ++t) optr[t + 1] += optr[t];
+        for (int64_t t = 0; t < d; ++t) fill[t] = optr[t];
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t h = xp[i]; h < xp[i + 1]; ++h) {
+                const int64_t q = fill[xi[h]]++;
+                oobj[q] = (int32_t)i;
+                oval[q] = (double)xv[h];
+            }
+        int64_t m_total = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            rho_a[i] = 0.0;   /* rho_max */
+            second[i] = 0.0;
+            out[i] = prev[i];
+        }
+        for (int32_t j = 0; j < k; ++j) {
+            for (int64_t i = 0; i < n; ++i) rho[i] = 0.0;
+            for (int64_t h = mp[j]; h < mp[j + 1]; ++h) {
+                const int32_t s = mi[h];
+                const double v = mv[h];
+                for (int64_t q = optr[s]; q < optr[s + 1]; ++q) {
+                    double p = v * oval[q];
+                    rho[oobj[q]] = rho[oobj[q]] + p;
+                }
+                m_total += optr[s + 1] - optr[s];
+            }
+            for (int64_t i = 0; i < n; ++i) {
+                if (rho[i] > rho_a[i]) {
+                    if (rho_a[i] > second[i]) second[i] = rho_a[i];
+                    rho_a[i] = rho[i];
+                    out[i] = j;
+                } else if (rho[i] > second[i]) {
+                    second[i] = rho[i];
+                }
+            }
+        }
+        int64_t zero_total = 0, changed = 0;
+        double obj = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (rho_a[i] == 0.0) ++zero_total;
+            changed += (out[i] != prev[i]);
+            obj += rho_a[i];
+            if (rho_2) rho_2[i] = second[i];
+        }
+        stats[0] = obj;
+        stats[1] = (double)changed;
+        stats[2] = (double)zero_total;
+        *mult = m_total;
+    }
+    free(optr); free(fill); free(oobj); free(oval); free(rho); free(second);
+    return err;
+}
+
+/*
  * oracle_scores: rho for listed (object, cluster) pairs, each computed by the
  * same ascending-term FP64 walk as oracle_assign (bit-identical to it).
  */

@@ -359,3 +359,83 @@ def test_scores_match_assignment_walk():
     idx = np.nonzero(ar.assign >= 0)[0]
     s = oracle.scores(x, m, idx, ar.assign[idx])
     assert np.array_equal(bits(s), bits(ar.rho[idx]))
+
+
+# ---------------------------------------------------------------------- IVFD
+# IVFD (Algorithm 4) inverts the objects and queries them with each mean.  For
+# a fixed (object, mean) pair it adds the same products in the same ascending
+# term order as the means-inverted walk, so its scores, its partition and its
+# multiplication count are those of Algorithm 3 in every iteration.
+def _second_best(rho, a):
+    """Largest score of any cluster other than the chosen one (0 if none)."""
+    out = np.zeros(rho.shape[0])
+    for i in range(rho.shape[0]):
+        r = rho[i].copy()
+        if a[i] >= 0:
+            r[a[i]] = 0.0
+        out[i] = max(0.0, float(r.max()))
+    return out
+
+
+@pytest.mark.parametrize("seed,n,d,k", [(71, 90, 160, 7), (72, 60, 40, 5), (73, 200, 120, 3)])
+def test_ivfd_assignment_bitwise_equals_dense_bruteforce(seed, n, d, k):
+    x = tiny(seed, n=n, d=d)
+    X = dense.to_dense(x)
+    means = oracle.initial_means(x, datagen.seed_objects(x, k, seed))
+    prev = np.full(n, -1, np.int32)
+    for _ in range(4):
+        ar = oracle.ivfd_assign(x, means, prev)
+        M = means.dense()
+        da, rho = dense.assign(X, M, prev)
+        assert np.array_equal(ar.assign, da)
+        chosen = np.where(da >= 0, rho[np.arange(n), np.maximum(da, 0)], 0.0)
+        assert np.array_equal(bits(ar.rho), bits(chosen))
+        assert np.array_equal(bits(ar.rho2), bits(_second_best(rho, da)))
+        # M = number of nonzero products, counted on the dense supports
+        assert ar.mult_adds == int(((X != 0).astype(np.int64) @ (M != 0).T.astype(np.int64)).sum())
+        assert ar.changed == int(np.sum(da != prev))
+        means, _ = oracle.update(x, k, ar.assign, means)
+        prev = ar.assign
+
+
+def test_ivfd_equals_ivf_in_every_iteration(medium_chain):
+    x, k, steps = medium_chain
+    prev = np.full(x.n, -1, np.int32)
+    for st in steps:
+        d = oracle.ivfd_assign(x, st.means_in, prev)
+        a = st.assign
+        assert np.array_equal(d.assign, a.assign)
+        assert np.array_equal(bits(d.rho), bits(a.rho))
+        assert np.array_equal(bits(d.rho2), bits(a.rho2))
+        assert d.mult_adds == a.mult_adds          # equal multiplication counts
+        assert d.objective == a.objective
+        assert (d.changed, d.zero_overlap) == (a.changed, a.zero_overlap)
+        prev = a.assign
+
+
+def test_ivfd_worked_example_golden():
+    rows, seeds, it = _parse_golden()
+    x = csr_from_rows(rows, 5)
+    means = oracle.initial_means(x, seeds)
+    prev = np.full(x.n, -1, np.int32)
+    for r in (1, 2, 3):
+        ar = oracle.ivfd_assign(x, means, prev)
+        assert ar.assign.tolist() == it[r]["assign"]
+        assert ar.mult_adds == it[r]["mult_adds"]
+        assert ar.objective == pytest.approx(it[r]["objective"], rel=4e-16, abs=0)
+        means, _ = oracle.update(x, 2, ar.assign, means)
+        prev = ar.assign
+
+
+def test_ivfd_ties_go_to_the_lowest_j_and_zero_overlap_keeps_previous():
+    x = tiny(53, n=80, d=60)
+    means = _duplicate_first(oracle.initial_means(x, datagen.seed_objects(x, 3, 53)))
+    prev = np.full(x.n, -1, np.int32)
+    ar = oracle.ivfd_assign(x, means, prev)
+    assert np.any(ar.assign == 0) and not np.any(ar.assign == 1)
+    rows = [{0: 1.0}, {1: 0.6, 2: 0.8}, {3: 1.0}, {0: 0.8, 1: 0.6}]
+    x = csr_from_rows(rows, 5)
+    means = _duplicate_first(oracle.initial_means(x, [1]))   # both means = object 1
+    ar = oracle.ivfd_assign(x, means, np.array([0, 1, 0, 0], np.int32))
+    assert ar.assign.tolist() == [0, 0, 0, 0]   # 0 and 2: no overlap, prev kept; 1, 3: tie -> 0
+    assert ar.rho[2] == 0.0 and ar.zero_overlap == 2

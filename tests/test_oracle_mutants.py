@@ -32,6 +32,17 @@ MUTANTS = {
     "sign_error": ("rho[f.cid[q]] = rho[f.cid[q]] + p;", "rho[f.cid[q]] = rho[f.cid[q]] - p;"),
     # zero-overlap objects reset to cluster 0 instead of keeping theirs
     "zero_overlap_reset": ("int32_t a = prev[i];", "int32_t a = 0;"),
+    # IVFD: the score vector cleared once instead of before every mean
+    "ivfd_rho_not_cleared": ("for (int64_t i = 0; i < n; ++i) rho[i] = 0.0;",
+                             "if (j == 0) for (int64_t i = 0; i < n; ++i) rho[i] = 0.0;"),
+    # IVFD: ">=" lets a later equal mean take the object
+    "ivfd_tie_rule": ("if (rho[i] > rho_a[i]) {", "if (rho[i] >= rho_a[i] && rho[i] > 0.0) {"),
+    # IVFD: objects without overlap reset to cluster 0
+    "ivfd_zero_overlap_reset": ("out[i] = prev[i];", "out[i] = 0;"),
+    # IVFD: one multiplication counted per posting list instead of per entry
+    "ivfd_mult_count": ("m_total += optr[s + 1] - optr[s];", "m_total += optr[s + 1] > optr[s];"),
+    # IVFD: the object's value replaced by 1 (the mean value alone is added)
+    "ivfd_missing_factor": ("double p = v * oval[q];", "double p = v;"),
     # an empty cluster is zeroed rather than kept
     "empty_cluster_dropped": ("tlen[j] = len;\n                    continue;", "tlen[j] = 0;\n                    continue;"),
 }
@@ -44,6 +55,9 @@ PIN_CHECKS = [
     pins.test_duplicate_initial_means_lowest_j_wins_and_empty_keeps_mean,
     pins.test_zero_overlap_object_keeps_previous,
     pins.test_k_equals_n_each_object_its_own_mean,
+    lambda: pins.test_ivfd_assignment_bitwise_equals_dense_bruteforce(71, 90, 160, 7),
+    pins.test_ivfd_worked_example_golden,
+    pins.test_ivfd_ties_go_to_the_lowest_j_and_zero_overlap_keeps_previous,
 ]
 
 

@@ -185,6 +185,31 @@ ivf_status ivf_converge(ivf_handle* h, int32_t max_iters, int32_t* assign, ivf_s
                         int32_t* iters_done);
 
 /*
+ * ivf_assign_ivfd: the assignment step of IVFD (the paper's Algorithm 4,
+ * Section "IVFD and IVF"): the OBJECTS are inverted and every mean, in
+ * ascending j, is a query whose scores for all objects are compared with each
+ * object's running maximum (strict ">" from 0, so the lowest j wins ties; an
+ * object sharing no term with any mean keeps its cluster).  It computes the
+ * same partition as ivf_assign (the two differ only in loop order) and is
+ * provided to measure which side is better inverted on this hardware.
+ *   objects_per_range  objects per LDS score tile: 4096, 8192 or 16384
+ *                      (0: 16384).  The objects' inverted file, range-major,
+ *                      is built on the first call (and again when this
+ *                      changes) and kept with the object set: nnz * 8 bytes
+ *                      plus (ranges * d + 1) * 4 bytes of device memory.
+ *   assign, stats      as for ivf_assign.  stats->mult_adds is the number of
+ *                      inverted-file entries the IVFD walk met, which equals
+ *                      M (the paper notes the two algorithms multiply equally
+ *                      often).  walk_ms times the IVFD walk kernel.
+ * The FP32 scores are certified and uncertified objects re-scored in FP64
+ * exactly as in ivf_assign (the re-score reads the means' inverted file the
+ * handle keeps).  Requires an FP32 handle (IVF_ERR_ARG otherwise), not a
+ * batch member (IVF_ERR_STATE), ranges x d < 2^32 (IVF_ERR_CAPACITY).
+ */
+ivf_status ivf_assign_ivfd(ivf_handle* h, int32_t objects_per_range, int32_t* assign,
+                           ivf_stats* stats);
+
+/*
  * ivf_get_means: two-call copy of the current means.  With out->indptr NULL
  * only out->k, out->d and out->nnz are filled; otherwise the caller's device
  * buffers (indptr[k+1], indices[nnz], values[nnz], nnz from the first call)

@@ -156,6 +156,16 @@ class IVFKMeans:
               self._h)
         return st.to_dict() if stats else None
 
+    def assign_ivfd(self, assign, objects_per_range=0, stats=True):
+        """The assignment step of IVFD (the objects inverted, each mean a
+        query): the same partition as ``assign``; FP32 handles only."""
+        import torch
+        _need_cuda(assign, torch.int32, "assign")
+        st = _lib.ivf_stats() if stats else None
+        check(_lib.get().ivf_assign_ivfd(self._h, int(objects_per_range), _ptr(assign),
+                                         ctypes.byref(st) if stats else None), self._h)
+        return st.to_dict() if stats else None
+
     def update(self, assign, stats=True):
         import torch
         _need_cuda(assign, torch.int32, "assign")

@@ -62,6 +62,7 @@ SIGNATURES = {
     "ivf_iterate": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_converge": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(ivf_stats),
                                ctypes.POINTER(c_int32)]),
+    "ivf_assign_ivfd": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_get_means": (c_int32, [c_void_p, ctypes.POINTER(ivf_means)]),
     "ivf_get_scores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ivf_get_plan": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),

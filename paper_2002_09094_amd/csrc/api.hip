@@ -111,8 +111,13 @@ struct ObjView {
     uint2* xt_tv = nullptr;
     int16_t* shift = nullptr;
     int64_t inexact = 0;
+    // IVFD: the objects' inverted file, range-major (built on first use)
+    int32_t o_nr = 0;           // objects per range, 0 = not built
+    int64_t o_R = 0;            // ranges
+    uint32_t* optr = nullptr;   // [o_R * d + 1]
+    uint2* opost = nullptr;     // [nnz]
 
-    void release() { dfree(xt_obj); dfree(xt_tv); dfree(shift); }
+    void release() { dfree(xt_obj); dfree(xt_tv); dfree(shift); dfree(optr); dfree(opost); }
 };
 
 }  // namespace
@@ -425,12 +430,13 @@ WalkArgs walk_args(ivf_handle* h) {
     return w;
 }
 
-// Assignment step after the walk: merge, FP64 re-score, objective.
-ivf_status assign_finish(ivf_handle* h, int32_t* assign) {
+// Assignment step after the walk: merge, FP64 re-score, objective.  R: the
+// range records per object (0: the plan's cluster ranges).
+ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0) {
     const hipStream_t s = h->stream;
     const Plan& p = h->plan;
     MergeArgs m{};
-    m.x_ptr = h->ov->x_ptr; m.n = h->n; m.R = p.R;
+    m.x_ptr = h->ov->x_ptr; m.n = h->n; m.R = R > 0 ? R : p.R;
     m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
     m.rec = h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
     m.best = h->best; m.best_id = h->best_id; m.second = h->second; m.flags = h->flags;
@@ -478,6 +484,39 @@ ivf_status assign_stats(ivf_handle* h, ivf_stats* stats, bool timed) {
     stats->nnz_means = h->nnzM_known ? h->nnzM : -1;
     stats->inexact_terms = h->ov->inexact;
     stats->update_ms = 0.f;
+    return IVF_OK;
+}
+
+// The objects' inverted file for IVFD with n_r objects per range, built
+// once per object set (and again if n_r changes).
+ivf_status ensure_object_ivf(ivf_handle* h, int32_t n_r) {
+    ObjView* ov = h->ov;
+    if (ov->o_nr == n_r) return IVF_OK;
+    dfree(ov->optr);
+    dfree(ov->opost);
+    ov->o_nr = 0;
+    const int64_t R = (h->n + n_r - 1) / n_r;
+    const int64_t nkeys = R * h->d;
+    if (nkeys + 1 >= ((int64_t)1 << 32))
+        return fail(h, IVF_ERR_CAPACITY, "IVFD: ranges x terms >= 2^32; use larger ranges");
+    ivf_status st = ensure_scratch(h, std::max<int64_t>(h->nnz, 1));
+    if (st != IVF_OK) return st;
+    HIPCHK(h, dalloc(&ov->optr, nkeys + 1));
+    HIPCHK(h, dalloc(&ov->opost, h->nnz));
+    int32_t* rowid = nullptr;
+    HIPCHK(h, dalloc(&rowid, h->nnz));
+    Scratch* sc = h->sc;
+    hipError_t e = launch_row_ids(ov->x_ptr, h->n, rowid, h->stream);
+    if (e == hipSuccess)
+        e = launch_ivfd_build(rowid, ov->x_idx, ov->x_val, h->nnz, n_r, h->d, nkeys, sc->keys,
+                              sc->vals, sc->keys_alt, sc->vals_alt, sc->iota, sc->tmp, ov->optr,
+                              ov->opost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    dfree(rowid);
+    if (e != hipSuccess)
+        return fail(h, IVF_ERR_HIP, std::string("IVFD build: ") + hipGetErrorString(e));
+    ov->o_nr = n_r;
+    ov->o_R = R;
     return IVF_OK;
 }
 
@@ -1137,6 +1176,46 @@ ivf_status ivf_converge(ivf_handle* h, int32_t max_iters, int32_t* assign, ivf_s
         e = run_update(h, assign, &st);
         if (e != IVF_OK) return e;
         if (per_iter) per_iter[r] = st;
+    }
+    return IVF_OK;
+}
+
+ivf_status ivf_assign_ivfd(ivf_handle* h, int32_t objects_per_range, int32_t* assign,
+                           ivf_stats* stats) {
+    if (!h || !assign) return fail(h, IVF_ERR_ARG, "null argument");
+    if (!h->has_means) return fail(h, IVF_ERR_STATE, "no means: call ivf_set_means or ivf_init_seeds");
+    if (h->opt.valtype != IVF_VAL_F32)
+        return fail(h, IVF_ERR_ARG, "IVFD scores in FP32: build the handle with FP32 values");
+    if (h->fixed) return fail(h, IVF_ERR_STATE, "capacities are fixed");
+    const int32_t n_r = objects_per_range > 0 ? objects_per_range : 16384;
+    if (n_r != 4096 && n_r != 8192 && n_r != 16384)
+        return fail(h, IVF_ERR_ARG, "objects_per_range must be 4096, 8192 or 16384");
+    ivf_status st = ensure_object_ivf(h, n_r);
+    if (st != IVF_OK) return st;
+    const hipStream_t s = h->stream;
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[0], s));
+    HIPCHK(h, launch_clear_counters(h->cnt, s));
+    HIPCHK(h, hipMemcpyAsync(h->prev, assign, sizeof(int32_t) * (size_t)h->n,
+                             hipMemcpyDeviceToDevice, s));
+    IvfdArgs a{};
+    a.optr = h->ov->optr; a.opost = h->ov->opost;
+    a.mm_ptr = h->mm_ptr[h->cur]; a.mm_idx = h->mm_idx[h->cur]; a.mm_val = h->mm_val[h->cur];
+    a.n = h->n; a.d = h->d; a.k = h->k; a.R = (int32_t)h->ov->o_R; a.n_r = n_r;
+    a.rec = h->rec; a.walked = &h->cnt->walked;
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[4], s));
+    HIPCHK(h, launch_ivfd_walk(a, s));
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[5], s));
+    HIPCHK(h, launch_ivfd_overlap(h->ov->x_ptr, h->ov->x_idx, h->n, h->ivf_ptr, h->rec, s));
+    st = assign_finish(h, assign, 1);
+    if (st != IVF_OK) return st;
+    if (stats) {
+        HIPCHK(h, hipEventRecord(h->ev[1], s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        st = assign_stats(h, stats, true);
+        if (st != IVF_OK) return st;
+        Counters c;
+        HIPCHK(h, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
+        stats->mult_adds = (int64_t)c.walked;   // counted by the walk itself
     }
     return IVF_OK;
 }

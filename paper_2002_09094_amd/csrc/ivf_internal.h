@@ -57,7 +57,8 @@ struct Counters {
     unsigned long long max_err_bits;   // max relative error (double bits, >= 0)
     unsigned long long max_bound_bits; // max objective bound (double bits, >= 0)
     unsigned long long error_flags;    // validation
-    unsigned long long pad[5];
+    unsigned long long walked;         // entries the IVFD walk met
+    unsigned long long pad[4];
 };
 
 // Error flags raised by the validation kernels.

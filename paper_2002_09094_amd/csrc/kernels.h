@@ -71,6 +71,35 @@ hipError_t launch_objective(const double* rho, const int32_t* assign, const int3
                             int64_t n, double* part, int nblocks, double* out, Counters* cnt,
                             hipStream_t s);
 
+// ------------------------------------------------------------------ IVFD walk
+// The assignment with the objects inverted: one workgroup per range of n_r
+// objects walks every mean over the range's slice of the objects' inverted
+// file and keeps the objects' running (best, cluster, second) in registers.
+struct IvfdArgs {
+    const uint32_t* optr;     // [R * d + 1] slice bounds, range-major then term
+    const uint2* opost;       // {object - range start, FP32 value bits}
+    const int64_t* mm_ptr;    // [k + 1] the means, mean-major FP64
+    const int32_t* mm_idx;
+    const double* mm_val;
+    int64_t n, d;
+    int32_t k, R, n_r;        // n_r in {4096, 8192, 16384}
+    RangeRec* rec;            // [n]: best, id, second (m comes from launch_ivfd_overlap)
+    unsigned long long* walked;   // entries walked, added
+};
+
+int ivfd_lds_bytes(int32_t n_r);
+// Objects' inverted file in (range, term, object) order from the row ids:
+// keys/vals/keys_alt/vals_alt/tmp are sort scratch of nnz entries, iota the
+// identity permutation, nkeys = R * d.
+hipError_t launch_ivfd_build(const int32_t* rowid, const int32_t* x_idx, const float* x_val,
+                             int64_t nnz, int32_t n_r, int64_t d, int64_t nkeys, uint32_t* keys,
+                             uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                             const uint32_t* iota, void* tmp, uint32_t* optr, uint2* post,
+                             hipStream_t s);
+hipError_t launch_ivfd_walk(const IvfdArgs& a, hipStream_t s);
+hipError_t launch_ivfd_overlap(const int64_t* x_ptr, const int32_t* x_idx, int64_t n,
+                               const int64_t* ivf_ptr, RangeRec* rec, hipStream_t s);
+
 // ----------------------------------------------------------------- update side
 struct ObjectView {
     const int64_t* x_ptr;

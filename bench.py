@@ -51,9 +51,9 @@ def iteration_bytes(m, nnz, n, nnz_means, valtype):
             + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
 
 
-def kernel_hash():
+def kernel_hash(source="assign.hip"):
     h = hashlib.sha256()
-    for f in ("assign.hip", "kernels.h", "ivf_internal.h"):
+    for f in (source, "kernels.h", "ivf_internal.h"):
         with open(os.path.join(ROOT, "paper_2002_09094_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -139,9 +139,11 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in launches]
         short = top.replace("ivf::(anonymous namespace)::", "").split("(")[0]
         lines += ["", "%s launches in order (ms): %s" % (short, ", ".join("%.3f" % v for v in ms))]
-        if len(ms) > 1:
+        if len(ms) > 1 and "::k_walk<" in top:
             lines.append("%s average over the launches after the first (the first iteration "
                          "starts from the seed means): %.3f ms" % (short, sum(ms[1:]) / (len(ms) - 1)))
+        elif ms:
+            lines.append("%s average over all launches: %.3f ms" % (short, sum(ms) / len(ms)))
         r0 = launches[0]
         lines.append("%s resources: VGPR %s, AGPR %s, SGPR %s, LDS %s bytes, workgroup %s, grid %s"
                      % (short, r0["VGPR_Count"], r0["Accum_VGPR_Count"], r0["SGPR_Count"],
@@ -150,15 +152,19 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         f.write("\n".join(lines) + "\n")
 
 
-def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, command):
-    """HBM traffic of the last walk launch from FETCH_SIZE and WRITE_SIZE runs
-    (KiB per dispatch), each scaled so that the calibration copy of COPY_BYTES
-    reads and writes exactly COPY_BYTES."""
+KERNEL_SOURCE = {"k_walk": "assign.hip", "k_ivfd_walk": "ivfd.hip"}
+
+
+def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, command,
+                       kernel="k_walk"):
+    """HBM traffic of the last launch of `kernel` from FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch), each scaled so that the calibration
+    copy of COPY_BYTES reads and writes exactly COPY_BYTES."""
     def pick(path, counter):
         rows = [r for r in _csv_rows(path) if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows
                   if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1e5][:3]
-        walks = [r for r in rows if "k_walk" in r["Kernel_Name"]]
+        walks = [r for r in rows if "::%s<" % kernel in r["Kernel_Name"]]
         return copies, walks
     fc, fw = pick(fetch_csv, "FETCH_SIZE")
     wc, ww = pick(write_csv, "WRITE_SIZE")
@@ -166,8 +172,9 @@ def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, comman
     w_scale = COPY_BYTES / (1024.0 * sum(wc) / len(wc))
     fetch = float(fw[-1]["Counter_Value"]) * 1024.0 * f_scale
     write = float(ww[-1]["Counter_Value"]) * 1024.0 * w_scale
-    out = {"kernel": "k_walk", "workload": workload, "valtype": valtype,
-           "kernel_hash": kernel_hash(), "fetch_bytes": fetch, "write_bytes": write,
+    out = {"kernel": kernel, "workload": workload, "valtype": valtype,
+           "kernel_hash": kernel_hash(KERNEL_SOURCE[kernel]), "fetch_bytes": fetch,
+           "write_bytes": write,
            "hbm_bytes_per_launch": fetch + write, "fetch_scale": f_scale,
            "write_scale": w_scale, "copy_fetch_kib": fc, "copy_write_kib": wc,
            "walk_fetch_kib_raw": float(fw[-1]["Counter_Value"]),
@@ -259,6 +266,94 @@ def run_figures(args):
                 break
         km.close()
         out["runs"].append(run)
+    print(json.dumps(out), flush=True)
+
+
+def calibration_copies():
+    """Three plain device copies of COPY_BYTES: the reference dispatches the
+    counter summaries scale FETCH_SIZE and WRITE_SIZE by."""
+    import torch
+
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    log("copy calibration: 3 x %d bytes" % COPY_BYTES)
+
+
+def _ivfd_compare(km, a, iters, n_r, tag):
+    """`iters` Lloyd iterations; each assignment runs twice from the same
+    means and previous partition: the means-inverted walk, then IVFD.  The
+    two partitions and multiplication counts must agree."""
+    import torch
+
+    rows = []
+    for r in range(iters):
+        prev = a.clone()
+        sa = km.assign(a)
+        b = prev.clone()
+        sd = km.assign_ivfd(b, objects_per_range=n_r)
+        same = bool(torch.equal(a, b))
+        if not same or sa["mult_adds"] != sd["mult_adds"]:
+            raise SystemExit("%s iteration %d: IVFD and IVF disagree" % (tag, r + 1))
+        km.update(a)
+        rows.append({"iter": r + 1, "mult_adds": sa["mult_adds"], "changed": sa["changed"],
+                     "ivf_walk_ms": sa["walk_ms"], "ivfd_walk_ms": sd["walk_ms"],
+                     "ivf_assign_ms": sa["assign_ms"], "ivfd_assign_ms": sd["assign_ms"],
+                     "ivfd_rescored": sd["rescored"], "ivf_rescored": sa["rescored"]})
+        log("%s iter %d: M %.3e, IVF walk %.1f ms, IVFD walk %.1f ms (x%.2f), same partition"
+            % (tag, r + 1, sa["mult_adds"], sa["walk_ms"], sd["walk_ms"],
+               sd["walk_ms"] / max(sa["walk_ms"], 1e-9)))
+    return rows
+
+
+def run_ivfd(args):
+    """Which side to invert (the paper's IVFD against IVF): the assignment
+    step with the objects inverted (each mean a query over them) against the
+    means inverted, on the same means, partition checked equal every
+    iteration.  First on the 8M-document workload at k = 10,000, then on the
+    1M-document PubMed-shaped set for k = 1,000 .. 20,000 (the paper's k
+    sweep).  Iterations after the first (which starts from seed means)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2002_09094_amd as ivf
+
+    dev = "cuda:0"
+    if args.calibrate_copy:
+        calibration_copies()
+    n_r = args.ivfd_range
+    out = {"metric": "IVFD vs IVF assignment walk time (same means, same partition)",
+           "objects_per_range": n_r, "runs": []}
+    sets = [("pubmed_8m", datagen.WORKLOADS["pubmed_8m"], [10000])]
+    if not args.ivfd_8m_only:
+        sets.append(("pubmed_1m", datagen.Workload("pubmed_1m", 1_000_000, 140_000, 60.0, 3, 1000,
+                                                   1.1, 0, 0, 9),
+                     [1000, 2000, 5000, 10000, 20000]))
+    for name, w, ks in sets:
+        x = w.generate()
+        xd = (torch.from_numpy(x.indptr).to(dev), torch.from_numpy(x.indices).to(dev),
+              torch.from_numpy(x.values).to(dev))
+        log("generated %s: n=%d d=%d nnz=%d" % (name, x.n, x.d, x.nnz))
+        for k in ks:
+            km = ivf.IVFKMeans(*xd, x.d, k)
+            km.init_seeds(torch.from_numpy(datagen.seed_objects(x, k, w.seed).astype(np.int32))
+                          .to(dev))
+            a = torch.full((x.n,), -1, dtype=torch.int32, device=dev)
+            km.assign(a)          # first iteration from the seed means: not timed
+            km.update(a)
+            rows = _ivfd_compare(km, a, args.steps, n_r, "%s k=%d" % (name, k))
+            ivf_ms = float(np.mean([r["ivf_walk_ms"] for r in rows]))
+            ivfd_ms = float(np.mean([r["ivfd_walk_ms"] for r in rows]))
+            out["runs"].append({"workload": name, "n": x.n, "d": x.d, "nnz": x.nnz, "k": k,
+                                "ivf_walk_ms": ivf_ms, "ivfd_walk_ms": ivfd_ms,
+                                "ratio": ivfd_ms / ivf_ms, "iters": rows})
+            km.close()
+        del xd
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
@@ -420,7 +515,7 @@ def main():
         summarize_pmc(*sys.argv[2:])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
-        print(json.dumps(summarize_counters(*sys.argv[2:8])))
+        print(json.dumps(summarize_counters(*sys.argv[2:9])))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,6 +528,10 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ivfd-range", type=int, default=16384,
+                    help="IVFD workload: objects per LDS tile (4096, 8192 or 16384)")
+    ap.add_argument("--ivfd-8m-only", action="store_true",
+                    help="IVFD workload: only the 8M-document set")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy 3 times (counter calibration)")
     args = ap.parse_args()
@@ -446,6 +545,9 @@ def main():
     if args.workload == "figures":
         run_figures(args)
         return
+    if args.workload == "ivfd":
+        run_ivfd(args)
+        return
 
     import numpy as np
     import torch
@@ -454,13 +556,7 @@ def main():
     import paper_2002_09094_amd as ivf
 
     if args.calibrate_copy:
-        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy calibration: 3 x %d bytes" % COPY_BYTES)
+        calibration_copies()
     w = datagen.WORKLOADS[args.workload]
     log("generating %s: n=%d d=%d lambda=%g k=%d" % (w.name, w.n, w.d, w.lam, w.k))
     x = w.generate()

@@ -201,9 +201,12 @@ ivf_status ivf_converge(ivf_handle* h, int32_t max_iters, int32_t* assign, ivf_s
  *                      inverted-file entries the IVFD walk met, which equals
  *                      M (the paper notes the two algorithms multiply equally
  *                      often).  walk_ms times the IVFD walk kernel.
- * The FP32 scores are certified and uncertified objects re-scored in FP64
- * exactly as in ivf_assign (the re-score reads the means' inverted file the
- * handle keeps).  Requires an FP32 handle (IVF_ERR_ARG otherwise), not a
+ * Scores are summed in fixed point (each FP32 product scaled by 2^F and
+ * rounded to an integer, F set from the largest object and mean norms so
+ * that no sum overflows 32 bits), certified with a bound for that rounding,
+ * and uncertified objects re-scored in FP64 as in ivf_assign (the re-score
+ * reads the means' inverted file the handle keeps).  Synchronises once to
+ * read the means' largest norm.  Requires an FP32 handle (IVF_ERR_ARG otherwise), not a
  * batch member (IVF_ERR_STATE), ranges x d < 2^32 (IVF_ERR_CAPACITY).
  */
 ivf_status ivf_assign_ivfd(ivf_handle* h, int32_t objects_per_range, int32_t* assign,

@@ -116,6 +116,7 @@ struct ObjView {
     int64_t o_R = 0;            // ranges
     uint32_t* optr = nullptr;   // [o_R * d + 1]
     uint2* opost = nullptr;     // [nnz]
+    double o_maxnorm = 0.0;     // largest object L2 norm
 
     void release() { dfree(xt_obj); dfree(xt_tv); dfree(shift); dfree(optr); dfree(opost); }
 };
@@ -163,6 +164,8 @@ struct ivf_handle {
     double* norm_part = nullptr;
     // assignment
     RangeRec* rec = nullptr;
+    RangeRec* ivfd_rec = nullptr;   // IVFD: one record per object and block of means
+    int64_t ivfd_rec_cap = 0;
     int32_t* prev = nullptr;
     int32_t* seed_assign = nullptr;
     double* rho = nullptr;
@@ -208,7 +211,7 @@ void free_handle(ivf_handle* h) {
     h->slab = nullptr;
     dfree(h->size); dfree(h->cstart); dfree(h->newcnt); dfree(h->scal);
     dfree(h->nrm); dfree(h->objpart); dfree(h->norm_items); dfree(h->norm_part);
-    dfree(h->rec); dfree(h->prev); dfree(h->seed_assign); dfree(h->rho); dfree(h->best);
+    dfree(h->rec); dfree(h->ivfd_rec); dfree(h->prev); dfree(h->seed_assign); dfree(h->rho); dfree(h->best);
     dfree(h->second); dfree(h->best_id); dfree(h->flags); dfree(h->rescore_list);
     dfree(h->part); dfree(h->dscal); dfree(h->cnt);
     for (auto& e : h->ev)
@@ -432,13 +435,17 @@ WalkArgs walk_args(ivf_handle* h) {
 
 // Assignment step after the walk: merge, FP64 re-score, objective.  R: the
 // range records per object (0: the plan's cluster ranges).
-ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0) {
+// R, rec, fixed_scale: records of another walk (IVFD's, R per object, of
+// fixed-point sums at that scale); 0 / null: the plan's cluster ranges.
+ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0,
+                         const RangeRec* rec = nullptr, double fixed_scale = 0.0) {
     const hipStream_t s = h->stream;
     const Plan& p = h->plan;
     MergeArgs m{};
     m.x_ptr = h->ov->x_ptr; m.n = h->n; m.R = R > 0 ? R : p.R;
     m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
-    m.rec = h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
+    m.fixed_scale = fixed_scale;
+    m.rec = rec ? rec : h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
     m.best = h->best; m.best_id = h->best_id; m.second = h->second; m.flags = h->flags;
     m.rescore_list = h->rescore_list; m.cnt = h->cnt;
     HIPCHK(h, launch_merge(m, s));
@@ -447,6 +454,7 @@ ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0) {
         r.w = walk_args(h);
         r.mm_ptr = h->mm_ptr[h->cur]; r.mm_idx = h->mm_idx[h->cur]; r.mm_val = h->mm_val[h->cur];
         r.valtype = h->opt.valtype;
+        r.fixed_scale = fixed_scale;
         r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
         r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
         HIPCHK(h, launch_rescore(r, h->rescore_waves, h->rescore_grid, s));
@@ -511,10 +519,16 @@ ivf_status ensure_object_ivf(ivf_handle* h, int32_t n_r) {
         e = launch_ivfd_build(rowid, ov->x_idx, ov->x_val, h->nnz, n_r, h->d, nkeys, sc->keys,
                               sc->vals, sc->keys_alt, sc->vals_alt, sc->iota, sc->tmp, ov->optr,
                               ov->opost, h->stream);
+    if (e == hipSuccess) e = launch_clear_counters(h->cnt, h->stream);
+    if (e == hipSuccess)
+        e = launch_max_row_norm(ov->x_ptr, ov->x_val, nullptr, h->n, &h->cnt->norm_bits, h->stream);
+    Counters c;
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost);
     dfree(rowid);
     if (e != hipSuccess)
         return fail(h, IVF_ERR_HIP, std::string("IVFD build: ") + hipGetErrorString(e));
+    std::memcpy(&ov->o_maxnorm, &c.norm_bits, sizeof(double));
     ov->o_nr = n_r;
     ov->o_R = R;
     return IVF_OK;
@@ -1193,6 +1207,29 @@ ivf_status ivf_assign_ivfd(ivf_handle* h, int32_t objects_per_range, int32_t* as
     ivf_status st = ensure_object_ivf(h, n_r);
     if (st != IVF_OK) return st;
     const hipStream_t s = h->stream;
+    const int32_t R = (int32_t)h->ov->o_R;
+    // blocks of means: about four workgroups per compute unit
+    const int32_t B = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>(h->k, (4 * (int64_t)h->cus + R - 1) / R));
+    if (h->n * (int64_t)B > h->ivfd_rec_cap) {
+        dfree(h->ivfd_rec);
+        h->ivfd_rec_cap = 0;
+        HIPCHK(h, dalloc(&h->ivfd_rec, h->n * (int64_t)B));
+        h->ivfd_rec_cap = h->n * (int64_t)B;
+    }
+    // fixed-point scale: every score is at most |x| |mu|, so with
+    // 2^F * max|x| * max|mu| <= 2^31 no sum (with its roundings) reaches 2^32
+    HIPCHK(h, launch_clear_counters(h->cnt, s));
+    HIPCHK(h, launch_max_row_norm(h->mm_ptr[h->cur], nullptr, h->mm_val[h->cur], h->k,
+                                  &h->cnt->norm_bits, s));
+    Counters cn;
+    HIPCHK(h, hipStreamSynchronize(s));
+    HIPCHK(h, hipMemcpy(&cn, h->cnt, sizeof(cn), hipMemcpyDeviceToHost));
+    double mnorm = 0.0;
+    std::memcpy(&mnorm, &cn.norm_bits, sizeof(double));
+    const double bound = h->ov->o_maxnorm * mnorm * (1.0 + 0x1p-20);
+    int F = 60;
+    if (bound > 0.0) F = std::min(60, std::max(-60, 31 - (int)std::ceil(std::log2(bound))));
     if (stats) HIPCHK(h, hipEventRecord(h->ev[0], s));
     HIPCHK(h, launch_clear_counters(h->cnt, s));
     HIPCHK(h, hipMemcpyAsync(h->prev, assign, sizeof(int32_t) * (size_t)h->n,
@@ -1200,13 +1237,15 @@ ivf_status ivf_assign_ivfd(ivf_handle* h, int32_t objects_per_range, int32_t* as
     IvfdArgs a{};
     a.optr = h->ov->optr; a.opost = h->ov->opost;
     a.mm_ptr = h->mm_ptr[h->cur]; a.mm_idx = h->mm_idx[h->cur]; a.mm_val = h->mm_val[h->cur];
-    a.n = h->n; a.d = h->d; a.k = h->k; a.R = (int32_t)h->ov->o_R; a.n_r = n_r;
-    a.rec = h->rec; a.walked = &h->cnt->walked;
+    a.n = h->n; a.d = h->d; a.k = h->k; a.R = R; a.n_r = n_r; a.B = B;
+    a.scale = std::ldexp(1.0f, F);
+    a.inv_scale = std::ldexp(1.0f, -F);
+    a.rec = h->ivfd_rec; a.walked = &h->cnt->walked;
     if (stats) HIPCHK(h, hipEventRecord(h->ev[4], s));
     HIPCHK(h, launch_ivfd_walk(a, s));
     if (stats) HIPCHK(h, hipEventRecord(h->ev[5], s));
-    HIPCHK(h, launch_ivfd_overlap(h->ov->x_ptr, h->ov->x_idx, h->n, h->ivf_ptr, h->rec, s));
-    st = assign_finish(h, assign, 1);
+    HIPCHK(h, launch_ivfd_overlap(h->ov->x_ptr, h->ov->x_idx, h->n, B, h->ivf_ptr, h->ivfd_rec, s));
+    st = assign_finish(h, assign, B, h->ivfd_rec, std::ldexp(1.0, F));
     if (st != IVF_OK) return st;
     if (stats) {
         HIPCHK(h, hipEventRecord(h->ev[1], s));

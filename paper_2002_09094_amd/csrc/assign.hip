@@ -414,7 +414,10 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
             atomicAdd(&a.cnt->zero_overlap, 1ull);
         } else {
             double c, ab, g;
-            cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], &c, &ab, &g);
+            if (a.fixed_scale > 0.0)
+                cert_consts_fixed(a.x_ptr[i + 1] - a.x_ptr[i], a.fixed_scale, &c, &ab, &g);
+            else
+                cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], &c, &ab, &g);
             const bool ok = !a.force_rescore && b > 0.f &&
                             cert_lb((double)b, c, ab, g) > cert_ub((double)s2, c, ab, g);
             if (ok || !a.certify) {
@@ -467,8 +470,8 @@ __device__ inline double exact_score(const RescoreArgs& a, int64_t hb, int64_t h
 
 // Objects the FP32 bound could not certify, one per wave.  The wave walks the
 // object again in FP32 (the same code, so the tile holds the scores the walk
-// had).  A cluster j is a candidate unless the bound proves it below the
-// FP32 winner: every non-candidate's FP64 score is then strictly smaller than
+// had).  A cluster j is a candidate unless the bounds prove it below the
+// FP32 winner (each score within its own walk's bound of the FP64 one): every non-candidate's FP64 score is then strictly smaller than
 // the winner's, so the FP64 argmax (lowest j on equal scores) is among the
 // candidates.  Candidates get their exact FP64 score and, in ascending j with
 // a strict test from 0, the reference's rule picks the cluster.
@@ -489,7 +492,16 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
         const int32_t fw = a.best_id[i];
         double c, ab, g;
         cert_consts(a.valtype, he - hb, &c, &ab, &g);
-        const double thr = cert_lb((double)a.best[i], c, ab, g);
+        // the winner's score may come from another walk (IVFD's fixed-point
+        // sums): its lower bound then uses that walk's constants
+        double thr;
+        if (a.fixed_scale > 0.0) {
+            double c1, ab1, g1;
+            cert_consts_fixed(he - hb, a.fixed_scale, &c1, &ab1, &g1);
+            thr = cert_lb((double)a.best[i], c1, ab1, g1);
+        } else {
+            thr = cert_lb((double)a.best[i], c, ab, g);
+        }
         double best = 0.0;
         int32_t bj = prev;
         double rho_fw = -1.0;   // FP64 score of the FP32 winner (always a candidate)

@@ -58,7 +58,8 @@ struct Counters {
     unsigned long long max_bound_bits; // max objective bound (double bits, >= 0)
     unsigned long long error_flags;    // validation
     unsigned long long walked;         // entries the IVFD walk met
-    unsigned long long pad[4];
+    unsigned long long norm_bits;      // largest row norm (double bits, >= 0)
+    unsigned long long pad[3];
 };
 
 // Error flags raised by the validation kernels.
@@ -94,6 +95,23 @@ __host__ __device__ inline void cert_consts(int valtype, int64_t nt, double* c, 
     // FP16 subnormal / flushed mean values: |m~ - m| <= 2^-25 absolutely; the
     // object's values are <= 1, so the score moves by at most nt * 2^-25.
     *a = (valtype == IVF_VAL_F16) ? n * 0x1p-25 * (1.0 + g32) * 1.01 : 0.0;
+    *g64 = (n * u64 / (1.0 - n * u64)) * 1.01 + 1e-17;
+}
+
+// Bound constants of a score summed in fixed point: the product of the
+// FP32-rounded mean value and the FP32 object value, rounded in FP32, scaled
+// by `scale` (a power of two) and rounded to the nearest integer; the nt
+// integers summed exactly; the sum converted to FP32 and divided by scale.
+// Relative: the two FP32 roundings before the sum and the one after; absolute:
+// half a unit of 1 / scale per product (plus the FP32 underflow spacing of a
+// product, 2^-149 each).  g64 as for cert_consts.
+__host__ __device__ inline void cert_consts_fixed(int64_t nt, double scale, double* c, double* a,
+                                                  double* g64) {
+    const double u32 = 0x1p-24, u64 = 0x1p-53;
+    const double n = (double)(nt > 0 ? nt : 1);
+    const double cc = (1.0 + u32) * (1.0 + u32) * (1.0 + u32) - 1.0;
+    *c = cc * 1.01 + 1e-15;
+    *a = n * (0.5 / scale + 0x1p-149) * (1.0 + u32) * 1.01;
     *g64 = (n * u64 / (1.0 - n * u64)) * 1.01 + 1e-17;
 }
 

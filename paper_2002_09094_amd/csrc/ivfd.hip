@@ -5,20 +5,26 @@
 // ">", means in ascending j, from 0).
 //
 // On this part the N-vector is tiled: a workgroup owns a range of n_r
-// objects (one FP32 score slot per object in LDS) and walks every mean over
-// the slice of the objects' inverted file that falls into its range.  The
-// file is therefore stored range-major: for range r and term s the entries
-// {object within the range, FP32 value} of the objects of r holding s, in
-// ascending object order, bounded by optr[r * d + s] .. optr[r * d + s + 1].
+// objects (one score slot per object in LDS) and a block of consecutive
+// means, and walks each mean over the slice of the objects' inverted file
+// that falls into its range.  The file is therefore stored range-major: for
+// range r and term s the entries {object within the range, FP32 value} of the
+// objects of r holding s, in ascending object order, bounded by
+// optr[r * d + s] .. optr[r * d + s + 1].
 //
-// A mean's terms are taken 1024 at a time (one per thread): each thread
-// loads its term's slice bounds, a workgroup scan lays the slices end to end
-// and the 16 waves split the concatenation evenly, so short slices (most of
-// them: a range holds few objects of a term) still fill all 64 lanes.  Waves
-// add into the shared tile with LDS float atomics.  The order of those adds
-// is not the FP64 reference's, which the certification bound allows (it holds
-// for any summation order of the nonnegative products).  The running
-// (best, cluster, second) of the workgroup's objects live in registers.
+// A mean's terms are taken 1024 at a time (one per thread): each thread loads
+// its term's slice bounds, a workgroup scan lays the nonempty slices end to
+// end and the 16 waves split the concatenation evenly, so short slices (most
+// of them: a range holds few objects of a term) still fill all 64 lanes.
+// Different terms reach the same object, so the adds into the shared tile
+// are LDS atomics, and in fixed point: an FP32 float atomic add to LDS runs
+// at a thirtieth of the rate of a 32-bit integer one on this part.  Each
+// product is scaled by 2^F and rounded to an integer; F is chosen from the
+// largest object and mean norms so that no score's sum can exceed 2^32.  The
+// integer sums are exact and independent of the order of the adds; the
+// certification bound accounts for the rounding (relative, from the FP32
+// products; absolute, half a unit of 2^-F per product).  The running (best,
+// cluster, second) of the workgroup's objects live in registers as integers.
 #include "kernels.h"
 
 namespace ivf {
@@ -69,9 +75,10 @@ __global__ void k_ivfd_post(const uint32_t* __restrict__ keys, const uint32_t* _
 
 // Entries every object meets over all means: the sum over its terms of the
 // number of means holding the term (the object's share of M, saturated at
-// 2^31 - 1; zero exactly when it shares no term with any mean).
+// 2^31 - 1; zero exactly when it shares no term with any mean), in the first
+// of its B records (0 in the others).
 __global__ void k_ivfd_overlap(const int64_t* __restrict__ x_ptr,
-                               const int32_t* __restrict__ x_idx, int64_t n,
+                               const int32_t* __restrict__ x_idx, int64_t n, int32_t B,
                                const int64_t* __restrict__ ivf_ptr, RangeRec* __restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -80,7 +87,22 @@ __global__ void k_ivfd_overlap(const int64_t* __restrict__ x_ptr,
         const int32_t t = x_idx[h];
         m += ivf_ptr[t + 1] - ivf_ptr[t];
     }
-    rec[i].m = (int32_t)std::min<int64_t>(m, 0x7fffffff);
+    rec[i * B].m = (int32_t)std::min<int64_t>(m, 0x7fffffff);
+    for (int32_t b = 1; b < B; ++b) rec[i * B + b].m = 0;
+}
+
+// Largest row norm, FP64 sums of squares in row order.
+__global__ void k_max_row_norm(const int64_t* __restrict__ ptr, const float* __restrict__ v32,
+                               const double* __restrict__ v64, int64_t rows,
+                               unsigned long long* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double s = 0.0;
+    for (int64_t h = ptr[i]; h < ptr[i + 1]; ++h) {
+        const double v = v64 ? v64[h] : (double)v32[h];
+        s = s + v * v;
+    }
+    if (s > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(sqrt(s)));
 }
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
@@ -92,37 +114,59 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x, int lane) {
     return x;
 }
 
-// One workgroup per range of NR = 4096 * G objects (4 G per thread).
+// First l in [lo, nt) with t_incl[l] > q, given t_incl[nt - 1] > q and
+// t_incl[lo - 1] <= q: a galloping search from lo (cheap when q has moved
+// past few slices, logarithmic when it has moved past many).
+__device__ inline int next_slice(const uint32_t* t_incl, int lo, int nt, uint32_t q) {
+    int step = 1, hi = lo;
+    while (t_incl[hi] <= q) {
+        lo = hi + 1;
+        hi = min(lo + step - 1, nt - 1);
+        step <<= 1;
+    }
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (t_incl[mid] > q) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// One workgroup per (range of NR = 4096 * G objects, block of means); 4 G
+// objects per thread.
 template <int G>
 __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
     constexpr int NR = 4096 * G;
     constexpr int S = 4 * G;   // objects per thread
-    extern __shared__ float4 lds4[];
-    float* tile = reinterpret_cast<float*>(lds4);
-    uint32_t* t_incl = reinterpret_cast<uint32_t*>(tile + NR);   // inclusive slice ends
-    uint32_t* t_off = t_incl + kIvfdThreads;                       // entry = t_off + position
+    extern __shared__ uint4 lds_u4[];
+    uint32_t* tile = reinterpret_cast<uint32_t*>(lds_u4);
+    uint32_t* t_incl = tile + NR;                 // inclusive ends of the nonempty slices
+    uint32_t* t_off = t_incl + kIvfdThreads;      // entry = t_off + position
     float* t_v = reinterpret_cast<float*>(t_off + kIvfdThreads);   // the term's mean value
-    uint32_t* w_sum = reinterpret_cast<uint32_t*>(t_v + kIvfdThreads);   // [kIvfdWaves + 1]
+    uint32_t* w_sum = reinterpret_cast<uint32_t*>(t_v + kIvfdThreads);   // [2 * kIvfdWaves + 2]
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int r = blockIdx.x;
+    const int r = blockIdx.x / a.B;
+    const int b = blockIdx.x - r * a.B;
+    const int32_t kb = (a.k + a.B - 1) / a.B;
+    const int32_t j0 = b * kb, j1 = min(a.k, j0 + kb);
     const uint32_t* __restrict__ optr = a.optr + (int64_t)r * a.d;
 
-    float best[S], sec[S];
+    uint32_t best[S], sec[S];
     int32_t bid[S];
 #pragma unroll
     for (int u = 0; u < S; ++u) {
-        best[u] = 0.f;
-        sec[u] = 0.f;
+        best[u] = 0u;
+        sec[u] = 0u;
         bid[u] = -1;
     }
 #pragma unroll
-    for (int g = 0; g < G; ++g) lds4[tid + kIvfdThreads * g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int g = 0; g < G; ++g) lds_u4[tid + kIvfdThreads * g] = make_uint4(0u, 0u, 0u, 0u);
     unsigned long long walked = 0;
     __syncthreads();
 
-    for (int32_t j = 0; j < a.k; ++j) {
+    for (int32_t j = j0; j < j1; ++j) {
         const int64_t jb = a.mm_ptr[j], je = a.mm_ptr[j + 1];
         for (int64_t sb = jb; sb < je; sb += kIvfdThreads) {
             // this thread's term: its slice in the range and the mean's value
@@ -135,38 +179,48 @@ __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
                 p0 = optr[s];
                 c = optr[s + 1] - p0;
             }
-            // workgroup scan of the slice lengths
+            // workgroup scans of the slice lengths and of the nonempty flags
+            const uint32_t f = c > 0 ? 1u : 0u;
             uint32_t incl = wave_incl_scan(c, lane);
-            if (lane == kWave - 1) w_sum[wv] = incl;
+            uint32_t fincl = wave_incl_scan(f, lane);
+            if (lane == kWave - 1) {
+                w_sum[wv] = incl;
+                w_sum[kIvfdWaves + wv] = fincl;
+            }
             __syncthreads();
             if (wv == 0) {
                 const uint32_t t = lane < kIvfdWaves ? w_sum[lane] : 0u;
+                const uint32_t tf = lane < kIvfdWaves ? w_sum[kIvfdWaves + lane] : 0u;
                 const uint32_t ti = wave_incl_scan(t, lane);
-                if (lane < kIvfdWaves) w_sum[lane] = ti - t;
-                if (lane == kIvfdWaves - 1) w_sum[kIvfdWaves] = ti;
+                const uint32_t tfi = wave_incl_scan(tf, lane);
+                if (lane < kIvfdWaves) {
+                    w_sum[lane] = ti - t;
+                    w_sum[kIvfdWaves + lane] = tfi - tf;
+                }
+                if (lane == kIvfdWaves - 1) {
+                    w_sum[2 * kIvfdWaves] = ti;
+                    w_sum[2 * kIvfdWaves + 1] = tfi;
+                }
             }
             __syncthreads();
             incl += w_sum[wv];
-            t_incl[tid] = incl;
-            t_off[tid] = p0 - (incl - c);   // modulo 2^32: p0 + (position - slice start)
-            t_v[tid] = v;
-            const uint32_t T = w_sum[kIvfdWaves];
+            if (f) {   // nonempty slices only, in term order
+                const uint32_t slot = fincl + w_sum[kIvfdWaves + wv] - 1;
+                t_incl[slot] = incl;
+                t_off[slot] = p0 - (incl - c);   // modulo 2^32: p0 + (position - slice start)
+                t_v[slot] = v;
+            }
+            const uint32_t T = w_sum[2 * kIvfdWaves];
+            const int nt = (int)w_sum[2 * kIvfdWaves + 1];
             __syncthreads();
             if (tid == 0) walked += T;
             // this wave's share [qa, qb) of the concatenated slices
             const uint32_t qa = (uint32_t)(((uint64_t)T * wv) / kIvfdWaves);
             const uint32_t qb = (uint32_t)(((uint64_t)T * (wv + 1)) / kIvfdWaves);
             if (qa < qb) {
-                // the slice holding the lane's first position: the first l
-                // with t_incl[l] > q; later positions only move forward
-                const uint32_t q1 = qa + lane;
-                int lo = 0, hi = kIvfdThreads - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (t_incl[mid] > q1) hi = mid;
-                    else lo = mid + 1;
-                }
-                int l = lo;
+                // t_incl[nt - 1] == T > every position below qb, so each
+                // search ends inside [0, nt)
+                int l = next_slice(t_incl, 0, nt, min(qa + lane, qb - 1));
                 for (uint32_t q0 = qa; q0 < qb; q0 += kWave * kIvfdUnroll) {
                     uint2 e[kIvfdUnroll];
                     float vv[kIvfdUnroll];
@@ -176,8 +230,7 @@ __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
                         vv[u] = 0.f;
                         e[u] = make_uint2(0u, 0u);
                         if (q < qb) {
-                            // t_incl of the last term is T > q: l stays in range
-                            while (t_incl[l] <= q) ++l;
+                            if (t_incl[l] <= q) l = next_slice(t_incl, l + 1, nt, q);
                             vv[u] = t_v[l];
                             e[u] = a.opost[t_off[l] + q];
                         }
@@ -185,7 +238,10 @@ __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
 #pragma unroll
                     for (int u = 0; u < kIvfdUnroll; ++u) {
                         const uint32_t q = q0 + u * kWave + lane;
-                        if (q < qb) atomicAdd(tile + e[u].x, vv[u] * __uint_as_float(e[u].y));
+                        if (q < qb) {
+                            const float p = vv[u] * __uint_as_float(e[u].y);
+                            atomicAdd(tile + e[u].x, __float2uint_rn(p * a.scale));
+                        }
                     }
                 }
             }
@@ -195,18 +251,18 @@ __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int gi = tid + kIvfdThreads * g;
-            const float4 t = lds4[gi];
-            lds4[gi] = make_float4(0.f, 0.f, 0.f, 0.f);
-            const float x[4] = {t.x, t.y, t.z, t.w};
+            const uint4 t = lds_u4[gi];
+            lds_u4[gi] = make_uint4(0u, 0u, 0u, 0u);
+            const uint32_t x[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int sl = 4 * g + u;
                 if (x[u] > best[sl]) {
-                    sec[sl] = fmaxf(sec[sl], best[sl]);
+                    sec[sl] = max(sec[sl], best[sl]);
                     best[sl] = x[u];
                     bid[sl] = j;
                 } else {
-                    sec[sl] = fmaxf(sec[sl], x[u]);
+                    sec[sl] = max(sec[sl], x[u]);
                 }
             }
         }
@@ -219,10 +275,11 @@ __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
         for (int u = 0; u < 4; ++u) {
             const int64_t o = obj0 + 4 * (int64_t)(tid + kIvfdThreads * g) + u;
             if (o < a.n) {
-                RangeRec* p = a.rec + o;
-                p->best = best[4 * g + u];
+                RangeRec* p = a.rec + o * a.B + b;
+                // an integer sum converted once (FP32 rounding) and scaled by 2^-F
+                p->best = (float)best[4 * g + u] * a.inv_scale;
                 p->id = bid[4 * g + u];
-                p->second = sec[4 * g + u];
+                p->second = (float)sec[4 * g + u] * a.inv_scale;
             }
         }
     if (tid == 0 && walked) atomicAdd(a.walked, walked);
@@ -237,7 +294,7 @@ const void* ivfd_kernel(int g) {
 }  // namespace
 
 int ivfd_lds_bytes(int32_t n_r) {
-    return n_r * 4 + 3 * kIvfdThreads * 4 + (kIvfdWaves + 1) * 4;
+    return n_r * 4 + 3 * kIvfdThreads * 4 + (2 * kIvfdWaves + 2) * 4;
 }
 
 hipError_t launch_ivfd_build(const int32_t* rowid, const int32_t* x_idx, const float* x_val,
@@ -268,15 +325,24 @@ hipError_t launch_ivfd_walk(const IvfdArgs& a, hipStream_t s) {
     hipError_t e = hipFuncSetAttribute(ivfd_kernel(g), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        lds);
     if (e != hipSuccess) return e;
-    if (g == 1) k_ivfd_walk<1><<<a.R, kIvfdThreads, lds, s>>>(a);
-    else if (g == 2) k_ivfd_walk<2><<<a.R, kIvfdThreads, lds, s>>>(a);
-    else k_ivfd_walk<4><<<a.R, kIvfdThreads, lds, s>>>(a);
+    if (a.B < 1 || (int64_t)a.R * a.B >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)(a.R * a.B);
+    if (g == 1) k_ivfd_walk<1><<<grid, kIvfdThreads, lds, s>>>(a);
+    else if (g == 2) k_ivfd_walk<2><<<grid, kIvfdThreads, lds, s>>>(a);
+    else k_ivfd_walk<4><<<grid, kIvfdThreads, lds, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_ivfd_overlap(const int64_t* x_ptr, const int32_t* x_idx, int64_t n,
+hipError_t launch_ivfd_overlap(const int64_t* x_ptr, const int32_t* x_idx, int64_t n, int32_t B,
                                const int64_t* ivf_ptr, RangeRec* rec, hipStream_t s) {
-    k_ivfd_overlap<<<grid_for(n), kThreads, 0, s>>>(x_ptr, x_idx, n, ivf_ptr, rec);
+    k_ivfd_overlap<<<grid_for(n), kThreads, 0, s>>>(x_ptr, x_idx, n, B, ivf_ptr, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_row_norm(const int64_t* ptr, const float* val32, const double* val64,
+                               int64_t rows, unsigned long long* out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    k_max_row_norm<<<grid_for(rows), kThreads, 0, s>>>(ptr, val32, val64, rows, out);
     return hipGetLastError();
 }
 

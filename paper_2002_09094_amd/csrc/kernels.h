@@ -24,6 +24,7 @@ struct MergeArgs {
     int64_t n;
     int32_t R;
     int32_t valtype, certify, force_rescore;
+    double fixed_scale;       // > 0: the records hold fixed-point sums (IVFD) of this scale
     const RangeRec* rec;
     const int32_t* prev;
     int32_t* assign;
@@ -42,6 +43,7 @@ struct RescoreArgs {
     const int32_t* mm_idx;
     const double* mm_val;
     int32_t valtype;
+    double fixed_scale;       // > 0: `best` is a fixed-point sum (IVFD) of this scale
     const int32_t* rescore_list;
     const int32_t* prev;
     int32_t* assign;
@@ -83,7 +85,9 @@ struct IvfdArgs {
     const double* mm_val;
     int64_t n, d;
     int32_t k, R, n_r;        // n_r in {4096, 8192, 16384}
-    RangeRec* rec;            // [n]: best, id, second (m comes from launch_ivfd_overlap)
+    int32_t B;                // blocks of consecutive means; workgroup = (range, block)
+    float scale, inv_scale;   // fixed-point scale 2^F of the products, and 2^-F
+    RangeRec* rec;            // [n * B]: best, id, second (m: launch_ivfd_overlap)
     unsigned long long* walked;   // entries walked, added
 };
 
@@ -97,8 +101,13 @@ hipError_t launch_ivfd_build(const int32_t* rowid, const int32_t* x_idx, const f
                              const uint32_t* iota, void* tmp, uint32_t* optr, uint2* post,
                              hipStream_t s);
 hipError_t launch_ivfd_walk(const IvfdArgs& a, hipStream_t s);
-hipError_t launch_ivfd_overlap(const int64_t* x_ptr, const int32_t* x_idx, int64_t n,
+// rec[i * B + b].m = the object's share of M for b == 0, else 0.
+hipError_t launch_ivfd_overlap(const int64_t* x_ptr, const int32_t* x_idx, int64_t n, int32_t B,
                                const int64_t* ivf_ptr, RangeRec* rec, hipStream_t s);
+// Largest L2 norm (FP64) of the rows of a CSR matrix with `rows` rows, as
+// double bits atomically maxed into *out (which the caller zeroes).
+hipError_t launch_max_row_norm(const int64_t* ptr, const float* val32, const double* val64,
+                               int64_t rows, unsigned long long* out, hipStream_t s);
 
 // ----------------------------------------------------------------- update side
 struct ObjectView {

@@ -257,6 +257,17 @@ ivf_status ivf_plan_shape(int32_t k, const ivf_options* opts, int32_t plan[7]);
  */
 ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]);
 
+/*
+ * ivf_cert_bound_fixed: the same constants for the fixed-point scores of
+ * ivf_assign_ivfd (host only): each FP32 product of the FP32-rounded mean
+ * value and the object value, times `scale` (a power of two), rounded to the
+ * nearest integer; the integers summed exactly; the sum converted to FP32 and
+ * divided by scale.  c[0] = ((1 + 2^-24)^3 - 1) * 1.01 + 1e-15, c[1] =
+ * nt * (1/(2 scale) + 2^-149) * (1 + 2^-24) * 1.01, c[2] as above.
+ * IVF_ERR_ARG for nt < 0 or a scale that is not a positive finite number.
+ */
+ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double c[3]);
+
 /* Frees the handle and everything it owns (NULL is a no-op). */
 void ivf_destroy(ivf_handle* h);
 

@@ -68,6 +68,14 @@ def cert_bound(valtype, nt):
     return tuple(c)
 
 
+def cert_bound_fixed(nt, scale):
+    """(c, a, g64) constants of IVFD's fixed-point scores (products scaled by
+    `scale` and rounded to integers) for an object of nt nonzeros."""
+    c = (ctypes.c_double * 3)()
+    check(_lib.get().ivf_cert_bound_fixed(int(nt), float(scale), c))
+    return tuple(c)
+
+
 class IVFKMeans:
     """One clustering instance on the current HIP device.
 

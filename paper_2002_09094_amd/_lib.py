@@ -68,6 +68,7 @@ SIGNATURES = {
     "ivf_get_plan": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "ivf_plan_shape": (c_int32, [c_int32, ctypes.POINTER(ivf_options), ctypes.POINTER(c_int32)]),
     "ivf_cert_bound": (c_int32, [c_int32, c_int64, ctypes.POINTER(c_double)]),
+    "ivf_cert_bound_fixed": (c_int32, [c_int64, c_double, ctypes.POINTER(c_double)]),
     "ivf_destroy": (None, [c_void_p]),
     "ivf_last_error": (ctypes.c_char_p, [c_void_p]),
     "ivf_status_str": (ctypes.c_char_p, [c_int32]),

@@ -1059,6 +1059,12 @@ ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]) {
     return IVF_OK;
 }
 
+ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double c[3]) {
+    if (!c || nt < 0 || !(scale > 0.0) || !std::isfinite(scale)) return IVF_ERR_ARG;
+    cert_consts_fixed(nt, scale, &c[0], &c[1], &c[2]);
+    return IVF_OK;
+}
+
 ivf_status ivf_build(const ivf_csr* X, int32_t k, const ivf_options* opts, ivf_handle** out) {
     if (out) *out = nullptr;
     if (!out) return fail(nullptr, IVF_ERR_ARG, "null argument");

@@ -144,3 +144,47 @@ def test_batch_build_rejects_bad_arguments_before_any_launch():
     assert b.value is None
     assert lib.ivf_batch_set_slack(None, 0.5, 0) == -1
     lib.ivf_batch_destroy(None)                           # no-op
+
+
+@pytest.mark.parametrize("below", [0, 7, 19])
+def test_fixed_point_bound_holds_for_emulated_ivfd_scores(below):
+    """Emulate IVFD's fixed-point scores on the CPU (mean value rounded to
+    FP32, FP32 product, product times 2^F rounded to the nearest integer,
+    exact integer sum, FP32 conversion, times 2^-F) and check the stated bound
+    against the exact score, with adversarial magnitudes, including products
+    far below 2^-F.  F is the library's choice from the two norms
+    (2^F |x| |mu| <= 2^31), or `below` bits less."""
+    rng = np.random.default_rng(5 + below)
+    for trial in range(300):
+        nt = int(rng.integers(1, 400))
+        v = rng.uniform(0, 1, nt) ** rng.uniform(1, 8)
+        v = (v / np.linalg.norm(v)).astype(np.float32)
+        v[v == 0] = np.float32(1e-30)
+        u = (rng.uniform(0, 1, nt) ** rng.uniform(1, 12)) * 10.0 ** -rng.uniform(0, 6)
+        u32 = u.astype(np.float32)
+        norms = float(np.linalg.norm(v.astype(np.float64))) * float(np.linalg.norm(u))
+        F = 31 - int(np.ceil(np.log2(norms * (1 + 2.0 ** -20)))) - below
+        S = np.float32(2.0 ** F)
+        q = 0
+        for t in range(nt):
+            p = np.float32(v[t] * u32[t])
+            q += int(np.rint(np.float32(p * S)))          # round half to even, as v_rndne
+        assert q < 2 ** 32
+        got = Fraction(float(np.float32(q))) / Fraction(2) ** F
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
+        c, a, g = ivf.cert_bound_fixed(nt, 2.0 ** F)
+        err = abs(got - exact)
+        assert err <= Fraction(c) * exact + Fraction(a), (F, trial, float(err), float(exact))
+
+
+def test_fixed_point_constants_and_arguments():
+    c, a, g = ivf.cert_bound_fixed(100, 2.0 ** 30)
+    u = Fraction(1, 2 ** 24)
+    assert c >= float(((1 + u) ** 3 - 1) * Fraction(101, 100))
+    assert a >= 100 * (0.5 / 2 ** 30) * 1.01
+    assert g >= float(_exact_gamma(100, Fraction(1, 2 ** 53)))
+    lib = _lib.get()
+    out = (ctypes.c_double * 3)()
+    assert lib.ivf_cert_bound_fixed(-1, 1.0, out) == -1
+    assert lib.ivf_cert_bound_fixed(5, 0.0, out) == -1
+    assert lib.ivf_cert_bound_fixed(5, float("inf"), out) == -1

@@ -92,7 +92,7 @@ typedef struct {
     int32_t force_rescore;  /* test hook: 1 = treat every object as uncertified */
     float dense_threshold;  /* a (term, range) slice holding at least this fraction of the
                                range's clusters is stored as a dense slab (zeros for absent
-                               clusters, no ids); 0: default 0.5; > 1: never dense */
+                               clusters, no ids); 0: default 0.35; > 1: never dense */
     void* stream;           /* hipStream_t; NULL = the null stream */
 } ivf_options;
 

@@ -314,7 +314,9 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
     a.k_r = h->plan.k_r;
     a.R = h->plan.R;
     a.valtype = h->opt.valtype;
-    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold : 0.5f;
+    // 0.35 measured fastest at 8M documents x k = 10,000 (FP32: 936 ms against
+    // 962 ms at 0.5 and 995 ms at 0.2; BF16 670 against 677 ms; FP16 flat)
+    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold : 0.35f;
     a.mm_idx = h->mm_idx[b];
     a.mm_val = h->mm_val[b];
     a.mm_row = h->mm_row[b];

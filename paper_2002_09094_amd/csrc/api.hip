@@ -726,9 +726,15 @@ ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err)
         if (err) *err = "k must be >= 1";
         return IVF_ERR_ARG;
     }
-    // 1280 clusters per tile and 8 tiles per workgroup (40 KB of LDS, 4
-    // workgroups and 32 waves per CU) measured best at 8M documents x k = 10,000
-    int32_t kr_max = (o && o->cluster_range > 0) ? o->cluster_range : 1280;
+    // Widest tile: 1024 clusters for FP32 values, 1280 for 16-bit ones (whose
+    // dense slabs are half the bytes), with 8 tiles per workgroup, measured
+    // best at 8M documents x k = 10,000 (FP32: 922 ms at 1000-cluster ranges
+    // against 935 ms at 1250 and 964 ms at 834; BF16: 655 ms at 1250 against
+    // 683 ms at 1000).  The hot set of a range, the dense slabs of its head
+    // terms, then about fills one XCD's 4 MB L2.
+    const int32_t vt = o ? o->valtype : IVF_VAL_F32;
+    int32_t kr_max = (o && o->cluster_range > 0) ? o->cluster_range
+                                                 : (vt == IVF_VAL_F32 ? 1024 : 1280);
     if (kr_max > 32768) {
         if (err) *err = "cluster_range above 32768 (LDS tile and 16-bit local ids)";
         return IVF_ERR_ARG;

@@ -45,7 +45,9 @@ def test_planner():
     p = ivf.plan_shape(100)
     assert p["ranges"] == 1 and p["k_r"] == 100
     p = ivf.plan_shape(10_000)
-    assert p["ranges"] * p["k_r"] >= 10_000 and p["k_r"] <= 1280 and p["waves"] == 8
+    assert p["ranges"] * p["k_r"] >= 10_000 and p["k_r"] <= 1024 and p["waves"] == 8
+    p = ivf.plan_shape(10_000, valtype="bf16")
+    assert p["ranges"] == 8 and p["k_r"] == 1250
     assert p["lds_bytes"] <= 160 * 1024
     p = ivf.plan_shape(50_000)
     assert p["ranges"] >= 40 and p["rescore_ranges"] == p["ranges"] and p["rescore_k_r"] == p["k_r"]

@@ -898,8 +898,9 @@ ivf_status batch_plan(ivf_batch* b, int32_t kr_max, int32_t waves) {
 // (clusters per tile, waves per workgroup) and keep the fastest.
 ivf_status batch_autotune(ivf_batch* b) {
     // 640-wide tiles measured slowest on every mix tried; wider tiles favour
-    // batches whose k spread past one 1280-wide range
-    static const int32_t cand[][2] = {{1280, 8}, {2560, 4}, {2560, 8}, {5120, 4}};
+    // batches whose k spread past one 1280-wide range, 1024 the FP32 walk of
+    // large k (the single-instance planner's choice)
+    static const int32_t cand[][2] = {{1024, 8}, {1280, 8}, {2560, 4}, {2560, 8}, {5120, 4}};
     const int32_t count = (int32_t)b->h.size();
     float best = 1e30f;
     int bi = 0;

@@ -147,7 +147,7 @@ def test_batch_multi_iteration_calls_and_tuning_report():
     stats = b.iterate(3, ba) + b.iterate(3, ba)           # eager, tuned, recorded, replayed
     assert len(stats) == 6 and all(len(s) == 2 for s in stats)
     tuning = b.tuning
-    assert len(tuning) == 4 and all(ms > 0 for (_, _, ms) in tuning)
+    assert len(tuning) == 5 and all(ms > 0 for (_, _, ms) in tuning)
     assert b.plan["kr_max"] == min(tuning, key=lambda t: t[2])[0]
     for i, (x, _, _, _, seeds) in enumerate(inst):
         ref = list(oracle.chain(x, seeds, 6))

@@ -134,7 +134,13 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
     hist[(int64_t)threadIdx.x * nt + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter: items are ranked in their input order (round, wave, lane).
+// Stable scatter of one tile of kTile items.  Items are ranked within the
+// tile by digit in their input order (round, wave, lane), placed in LDS in
+// that order, and written out digit run by digit run: consecutive threads
+// write consecutive addresses of a run, where writing each item straight to
+// its bucket touched one cache line per item.  The tile's count of digit d
+// is the difference of consecutive entries of the scanned histogram (laid
+// out digit-major, tile-minor), the last entry's against n.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint32_t* __restrict__ keys, const V* __restrict__ vals, int64_t n,
@@ -142,10 +148,25 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     uint32_t* __restrict__ okeys, V* __restrict__ ovals) {
     constexpr int W = kBlock / kWave;
     n = bounded_count(n, n_dev);
-    __shared__ uint32_t run[kDigits];
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ V s_vals[kTile];
+    __shared__ uint32_t run[kDigits];      // next local slot of each digit
+    __shared__ uint32_t start[kDigits];    // local start of each digit's run
+    __shared__ uint32_t glob[kDigits];     // global start of this tile's run of each digit
     __shared__ uint32_t wcnt[W][kDigits];
+    __shared__ uint32_t sh[kBlock / kWave + 1];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    run[tid] = offs[(int64_t)tid * nt + blockIdx.x];
+    {
+        const int64_t idx = (int64_t)tid * nt + blockIdx.x;
+        const uint32_t g = offs[idx];
+        const uint32_t next = idx + 1 < (int64_t)kDigits * nt ? offs[idx + 1] : (uint32_t)n;
+        uint32_t total;
+        const uint32_t st = block_exclusive_scan<uint32_t>(next - g, sh, &total);
+        glob[tid] = g;
+        start[tid] = st;
+        run[tid] = st;
+    }
+    __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kTile;
     for (int r = 0; r < kItems; ++r) {
@@ -181,10 +202,23 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         __syncthreads();
         if (valid) {
             const uint32_t pos = wcnt[w][d] + rank;
-            okeys[pos] = key;
-            ovals[pos] = val;
+            if (pos < (uint32_t)kTile) {
+                s_keys[pos] = key;
+                s_vals[pos] = val;
+            }
         }
         __syncthreads();
+    }
+    // the tile in digit order: runs of consecutive addresses
+    const int64_t items = std::min<int64_t>(kTile, std::max<int64_t>(0, n - base));
+    for (int p = tid; p < items; p += kBlock) {
+        const uint32_t key = s_keys[p];
+        const uint32_t d = (key >> shift) & (kDigits - 1);
+        const int64_t pos = (int64_t)glob[d] + (p - (int64_t)start[d]);
+        if (pos >= 0 && pos < n) {
+            okeys[pos] = key;
+            ovals[pos] = s_vals[p];
+        }
     }
 }
 

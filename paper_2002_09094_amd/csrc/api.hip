@@ -773,7 +773,18 @@ ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err)
 struct ivf_batch {
     std::vector<ivf_handle*> h;
     std::vector<ObjView*> views;
-    Scratch* sc = nullptr;
+    // After the walk, the instances' merges and updates run on kLanes streams,
+    // forked from and joined back into the batch stream; small instances
+    // leave most of the GPU idle on their own.  Instances go to lanes largest
+    // first, each to the lane with the fewest object nonzeros so far.  Each
+    // lane has its own sort/segment scratch, sized for its largest instance:
+    // instances of one lane run one after another.
+    static constexpr int kLanes = 4;
+    Scratch* lane_sc[kLanes] = {};
+    hipStream_t lane[kLanes] = {};
+    std::vector<int> lane_of;   // per instance
+    hipEvent_t fork_ev = nullptr;
+    hipEvent_t join_ev[kLanes] = {};
     ivf_options opt{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -942,14 +953,25 @@ ivf_status batch_iteration(ivf_batch* b, int32_t* const* assign, bool eager) {
                               b->waves, b->grid, b->d_work, s));
     k_stamp<<<1, 64, 0, s>>>(b->d_stamp + 1);
     BHIP(b, hipGetLastError());
-    for (int32_t i = 0; i < count; ++i) {
-        ivf_status st = assign_finish(b->h[i], assign[i]);
-        if (st != IVF_OK) return bfail(b, st, b->h[i]->err);
+    // merges and updates on the lanes: fork after the walk, join before returning
+    BHIP(b, hipEventRecord(b->fork_ev, s));
+    for (int l = 0; l < ivf_batch::kLanes; ++l) BHIP(b, hipStreamWaitEvent(b->lane[l], b->fork_ev, 0));
+    ivf_status st = IVF_OK;
+    int32_t failed = -1;
+    for (int32_t i = 0; i < count && st == IVF_OK; ++i) {
+        ivf_handle* h = b->h[i];
+        h->stream = b->lane[b->lane_of[i]];
+        st = assign_finish(h, assign[i]);
+        if (st == IVF_OK) st = run_update(h, assign[i], nullptr, false);
+        h->stream = s;
+        if (st != IVF_OK) failed = i;
     }
-    for (int32_t i = 0; i < count; ++i) {
-        ivf_status st = run_update(b->h[i], assign[i], nullptr, false);
-        if (st != IVF_OK) return bfail(b, st, b->h[i]->err);
+    // the join is recorded on every path, so a capture always ends joined
+    for (int l = 0; l < ivf_batch::kLanes; ++l) {
+        BHIP(b, hipEventRecord(b->join_ev[l], b->lane[l]));
+        BHIP(b, hipStreamWaitEvent(s, b->join_ev[l], 0));
     }
+    if (st != IVF_OK) return bfail(b, st, b->h[failed]->err);
     if (eager) return upload_args(b);   // slab pointers may have moved
     return IVF_OK;
 }
@@ -1356,12 +1378,33 @@ ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
     int dev = 0;
     BHIP(b, hipGetDevice(&dev));
     BHIP(b, hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
-    b->sc = new (std::nothrow) Scratch();
-    if (!b->sc) return bail(bfail(b, IVF_ERR_OOM, "host allocation failed"));
-    // the shared scratch is sized for the largest instance up front
-    int64_t maxnnz = 1;
-    for (int32_t i = 0; i < count; ++i) maxnnz = std::max(maxnnz, X[i].nnz);
-    BHIP(b, b->sc->ensure(maxnnz, maxnnz, 1, b->stream));
+    {
+        std::vector<int32_t> order(count);
+        for (int32_t i = 0; i < count; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t c) { return X[a].nnz > X[c].nnz; });
+        int64_t load[ivf_batch::kLanes] = {};
+        b->lane_of.assign(count, 0);
+        for (int32_t i : order) {
+            int best = 0;
+            for (int l = 1; l < ivf_batch::kLanes; ++l)
+                if (load[l] < load[best]) best = l;
+            b->lane_of[i] = best;
+            load[best] += X[i].nnz + 1;
+        }
+    }
+    for (int l = 0; l < ivf_batch::kLanes; ++l) {
+        BHIP(b, hipStreamCreate(&b->lane[l]));   // default priority
+        BHIP(b, hipEventCreateWithFlags(&b->join_ev[l], hipEventDisableTiming));
+        b->lane_sc[l] = new (std::nothrow) Scratch();
+        if (!b->lane_sc[l]) return bail(bfail(b, IVF_ERR_OOM, "host allocation failed"));
+        // a lane's scratch is sized for its largest instance up front
+        int64_t maxnnz = 1;
+        for (int32_t i = 0; i < count; ++i)
+            if (b->lane_of[i] == l) maxnnz = std::max(maxnnz, X[i].nnz);
+        BHIP(b, b->lane_sc[l]->ensure(maxnnz, maxnnz, 1, b->stream));
+    }
+    BHIP(b, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
     ivf_options oi = b->opt;
     oi.cluster_range = o.cluster_range > 0 ? o.cluster_range : 1280;
     oi.waves_per_wg = 1;
@@ -1373,7 +1416,7 @@ ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
                 X[j].nnz == X[i].nnz)
                 ov = b->h[j]->ov;
         ivf_handle* h = nullptr;
-        ivf_status st = create_handle(&X[i], k[i], oi, b->sc, ov, &h);
+        ivf_status st = create_handle(&X[i], k[i], oi, b->lane_sc[b->lane_of[i]], ov, &h);
         if (st != IVF_OK) return bail(bfail(b, st, g_build_error));
         h->owns_sc = false;
         if (!ov) {   // the batch owns every view; handles only borrow
@@ -1561,6 +1604,8 @@ ivf_status ivf_batch_get_tuning(const ivf_batch* b, int32_t cap, int32_t* shapes
 void ivf_batch_destroy(ivf_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (int l = 0; l < ivf_batch::kLanes; ++l)
+        if (b->lane[l]) (void)hipStreamSynchronize(b->lane[l]);
     drop_graphs(b);
     for (ivf_handle* h : b->h) {
         free_handle(h);
@@ -1570,7 +1615,13 @@ void ivf_batch_destroy(ivf_batch* b) {
         v->release();
         delete v;
     }
-    if (b->sc) { b->sc->release(); delete b->sc; }
+    for (int l = 0; l < ivf_batch::kLanes; ++l) {
+        if (b->lane[l]) (void)hipStreamSynchronize(b->lane[l]);
+        if (b->lane_sc[l]) { b->lane_sc[l]->release(); delete b->lane_sc[l]; }
+        if (b->lane[l]) (void)hipStreamDestroy(b->lane[l]);
+        if (b->join_ev[l]) (void)hipEventDestroy(b->join_ev[l]);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     dfree(b->d_args);
     dfree(b->d_item_off);
     dfree(b->d_flags);

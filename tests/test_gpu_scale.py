@@ -24,13 +24,13 @@ if not torch.cuda.is_available():
 import paper_2002_09094_amd as ivf  # noqa: E402
 from gpu_util import DEV, i32, means_to_dev, to_dev  # noqa: E402
 
-REPORT_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                          "gpurun_out")
+# measured numbers are also written as JSON files into $IVF_REPORT_DIR, if set
+REPORT_DIR = os.environ.get("IVF_REPORT_DIR", "")
 
 
 def _report(name, payload):
     print(name, json.dumps(payload), flush=True)
-    if os.path.isdir(REPORT_DIR):
+    if REPORT_DIR and os.path.isdir(REPORT_DIR):
         with open(os.path.join(REPORT_DIR, name + ".json"), "w") as f:
             json.dump(payload, f, indent=1)
 

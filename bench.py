@@ -100,7 +100,7 @@ def cpu_baseline(x, k, seed, target_s):
             break
         s = int(min(x.n, max(2 * s, s * target_s / max(dt, 1e-3))))
     rate = r.mult_adds / dt
-    return {
+    out = {
         "value": rate / m_full,
         "unit": "iter/s",
         "cores": threads,
@@ -109,7 +109,76 @@ def cpu_baseline(x, k, seed, target_s):
                    "means of a seeded random partition (k=%d), %.1fs; scaled by the full "
                    "set's exact mult-add count %d" % (s, x.n, k, dt, m_full)),
         "mult_adds_per_s": rate,
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
     }
+    out.update(single_core_small())
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def single_core_small():
+    """The oracle on one core over the small workload (20,000 documents,
+    k = 100): the second Lloyd iteration's assignment + update, beside the
+    paper's single-thread figures."""
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    w = datagen.WORKLOADS["small"]
+    x = w.generate()
+    seeds = w.seeds(x)
+    means = oracle.initial_means(x, seeds)
+    prev = np.full(x.n, -1, np.int32)
+    times = []
+    for _ in range(2):
+        t = time.perf_counter()
+        r = oracle.assign(x, means, prev, threads=1)
+        means, _ = oracle.update(x, w.k, r.assign, means, threads=1)
+        times.append(time.perf_counter() - t)
+        prev = r.assign
+    log("cpu baseline: small workload on one core, %.3f s per iteration" % times[-1])
+    return {"single_core_small_s_per_iter": times[-1], "single_core_small_mult_adds": r.mult_adds}
+
+
+def stream_gbps(nbytes=2 << 30, reps=5):
+    """Streaming bandwidth of this GPU, bytes read + written per second over
+    2 GiB arrays: a copy (c = a) and STREAM's add (c = a + b), the practical
+    HBM ceilings next to the nominal 8 TB/s."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a).fill_(2.0)
+    c = torch.empty_like(a)
+
+    def timed(f):
+        for _ in range(2):
+            f()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    copy = 2.0 * nbytes * reps / timed(lambda: c.copy_(a)) / 1e9
+    add = 3.0 * nbytes * reps / timed(lambda: torch.add(a, b, out=c)) / 1e9
+    del a, b, c
+    torch.cuda.empty_cache()
+    log("stream: copy %.1f GB/s, add %.1f GB/s (read + write)" % (copy, add))
+    return copy, add
 
 
 def _csv_rows(path):
@@ -373,6 +442,7 @@ def run_batched(args):
     import paper_2002_09094_amd as ivf
 
     dev = "cuda:0"
+    copy_gbps, add_gbps = stream_gbps()
     inst = datagen.batched_instances()
     data = {}
     for w, _ in inst:
@@ -476,6 +546,8 @@ def run_batched(args):
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": None,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+            "stream_copy_gbps": copy_gbps,
+            "stream_add_gbps": add_gbps,
         },
     }
     b.close()
@@ -557,6 +629,7 @@ def main():
 
     if args.calibrate_copy:
         calibration_copies()
+    copy_gbps, add_gbps = stream_gbps()
     w = datagen.WORKLOADS[args.workload]
     log("generating %s: n=%d d=%d lambda=%g k=%d" % (w.name, w.n, w.d, w.lam, w.k))
     x = w.generate()
@@ -578,10 +651,13 @@ def main():
                sa["rescored"]))
     torch.cuda.synchronize()
     per = []
+    step_ms = []
     t_start = time.perf_counter()
     for r in range(args.steps):
+        t0 = time.perf_counter()
         sa = km.assign(a)
-        su = km.update(a)
+        su = km.update(a)         # both calls synchronise: the step's wall time
+        step_ms.append(1e3 * (time.perf_counter() - t0))
         per.append((sa, su))
         log("step %d: assign %.1f ms (walk %.1f), update %.1f ms, M=%.3e, certified=%d, "
             "rescored=%d, changed=%d" % (r, sa["assign_ms"], sa["walk_ms"], su["update_ms"],
@@ -608,6 +684,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": 1e3 * t_total / args.steps,
+        "median_ms_per_step": float(np.median(step_ms)),
+        "step_ms": step_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -638,6 +716,10 @@ def main():
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
             "traffic_gbps": traffic_gbps,
             "traffic_frac": traffic_gbps / HBM_PEAK_GBPS if traffic_gbps else None,
+            "stream_copy_gbps": copy_gbps,
+            "stream_add_gbps": add_gbps,
+            "traffic_frac_of_stream": (traffic_gbps / max(copy_gbps, add_gbps)
+                                       if traffic_gbps else None),
         },
     }
     km.close()

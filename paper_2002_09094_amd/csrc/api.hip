@@ -275,7 +275,7 @@ ivf_status ensure_ivf(ivf_handle* h, int64_t need) {
         h->post = nullptr;
         h->ivf_cap = 0;
         HIPCHK(h, dalloc(&h->cid, cap));
-        HIPCHK(h, hipMalloc(&h->post, (size_t)post_bytes(std::max<int64_t>(cap, 1))));
+        HIPCHK(h, hipMalloc(&h->post, (size_t)std::max<int64_t>(cap, 1) * 8));
         h->ivf_cap = cap;
     }
     return ensure_scratch(h, need);
@@ -330,8 +330,6 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
     a.dsz = h->dsz;
     a.cid = h->cid;
     a.post = h->post;
-    a.post_val = reinterpret_cast<float*>(reinterpret_cast<char*>(h->post) +
-                                          post_val_offset(h->ivf_cap));
     a.slab = h->slab;
     a.tmp = h->sc->tmp;
     return a;
@@ -431,8 +429,6 @@ WalkArgs walk_args(ivf_handle* h) {
     WalkArgs w{};
     w.x_ptr = h->ov->x_ptr; w.x_idx = h->ov->x_idx; w.x_val = h->ov->x_val; w.n = h->n;
     w.desc = h->desc; w.post = h->post; w.slab = h->slab;
-    w.post_val = reinterpret_cast<const float*>(reinterpret_cast<const char*>(h->post) +
-                                                post_val_offset(h->ivf_cap));
     w.k = h->k; w.k_r = p.k_r; w.R = p.R; w.chunk = p.chunk; w.tile_stride = p.tile_stride;
     w.items_per_range = (h->n + p.chunk - 1) / p.chunk;
     w.cnt = h->cnt; w.rec = h->rec;

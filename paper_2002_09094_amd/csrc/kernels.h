@@ -1,8 +1,6 @@
 // Argument blocks and launch wrappers of the device kernels.
 #pragma once
 
-#include <algorithm>
-
 #include "ivf_internal.h"
 
 namespace ivf {
@@ -13,8 +11,7 @@ struct WalkArgs {
     const float* x_val;
     int64_t n;
     const SliceDesc* desc;    // [d * R]: per (term, range) slice, sparse or dense
-    const void* post;         // FP32: uint16 local cluster; 16-bit: uint32 {local cluster | value}
-    const float* post_val;    // FP32: the entries' values (a second array in the same buffer)
+    const void* post;         // uint2 {cluster, f32} or uint32 {local cluster | 16-bit value}
     const void* slab;         // dense slices: float or 16-bit values, zeros for absent clusters
     int32_t k, k_r, R, chunk, tile_stride;
     int64_t items_per_range;  // ceil(n / chunk)
@@ -213,17 +210,9 @@ struct IvfArgs {
     int64_t* dsz;        // [d * R + 1] dense slab sizes, then their offsets (scanned)
     void* slab;          // dense slabs (sized by the first phase)
     int32_t* cid;        // [nnzM]
-    void* post;          // [nnzM] uint16 local cluster (FP32 values) or uint32 {local | value}
-    float* post_val;     // [nnzM] FP32 values
+    void* post;          // [nnzM] uint2 or uint32
     void* tmp;
 };
-
-// FP32 postings are two arrays in one buffer of `cap` entries: 16-bit local
-// cluster ids, then (256-byte aligned) the FP32 values: 6 bytes per entry.
-inline int64_t post_val_offset(int64_t cap) { return (cap * 2 + 255) / 256 * 256; }
-inline int64_t post_bytes(int64_t cap) {
-    return std::max<int64_t>(cap * 4, post_val_offset(cap) + cap * 4);
-}
 
 // Inverted-file rebuild, phase 1: stable sort of the mean entries by term,
 // lists in ascending cluster order with the stored-precision values, slice

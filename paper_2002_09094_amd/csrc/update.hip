@@ -457,7 +457,7 @@ __device__ inline uint32_t bf16_rne(float f) {
 __global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __restrict__ mm_row,
                            const double* __restrict__ mm_val, int64_t nnzM, const int64_t* n_dev,
                            int32_t k_r, int valtype, int32_t* __restrict__ cid,
-                           void* __restrict__ post, float* __restrict__ post_val) {
+                           void* __restrict__ post) {
     nnzM = bounded_count(nnzM, n_dev);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
          q += (int64_t)gridDim.x * blockDim.x) {
@@ -467,8 +467,7 @@ __global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __r
         cid[q] = j;
         const float f = (float)u;
         if (valtype == IVF_VAL_F32) {
-            reinterpret_cast<uint16_t*>(post)[q] = (uint16_t)(j % k_r);
-            post_val[q] = f;
+            reinterpret_cast<uint2*>(post)[q] = make_uint2((uint32_t)j, __float_as_uint(f));
         } else {
             const uint32_t local = (uint32_t)(j % k_r);
             uint32_t h;
@@ -535,8 +534,7 @@ __global__ void k_zero_t(T* p, int64_t n, const int64_t* n_dev = nullptr) {
 
 // Dense slabs take every entry of their slice at its cluster's offset.
 __global__ void k_slab_scatter(const uint32_t* __restrict__ skeys, const int32_t* __restrict__ cid,
-                               const void* __restrict__ post, const float* __restrict__ post_val,
-                               const SliceDesc* __restrict__ desc,
+                               const void* __restrict__ post, const SliceDesc* __restrict__ desc,
                                int64_t nnzM, const int64_t* n_dev, int64_t d, int32_t k,
                                int32_t R, int32_t k_r, int valtype, void* __restrict__ slab) {
     nnzM = bounded_count(nnzM, n_dev);
@@ -550,7 +548,8 @@ __global__ void k_slab_scatter(const uint32_t* __restrict__ skeys, const int32_t
         if (pos >= 0) continue;
         const int64_t at = (-pos - 1) + (j - r * k_r);
         if (valtype == IVF_VAL_F32)
-            reinterpret_cast<float*>(slab)[at] = post_val[q];
+            reinterpret_cast<float*>(slab)[at] =
+                __uint_as_float(reinterpret_cast<const uint2*>(post)[q].y);
         else
             reinterpret_cast<uint16_t*>(slab)[at] =
                 (uint16_t)(reinterpret_cast<const uint32_t*>(post)[q] >> 16);
@@ -697,7 +696,7 @@ hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
                                  a.nnz_dev));
         k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM,
                                                        a.nnz_dev, a.k_r, a.valtype, a.cid,
-                                                       a.post, a.post_val);
+                                                       a.post);
         HIP_RET(hipGetLastError());
     }
     k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.nnz_dev, a.d, a.ivf_ptr);
@@ -720,9 +719,9 @@ hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_cap, hipStream_t s) {
         k_zero_t<uint16_t><<<capped(slab_cap), kThreads, 0, s>>>(
             reinterpret_cast<uint16_t*>(a.slab), slab_cap, total);
     if (a.nnzM > 0)
-        k_slab_scatter<<<capped(a.nnzM), kThreads, 0, s>>>(a.keys, a.cid, a.post, a.post_val,
-                                                           a.desc, a.nnzM, a.nnz_dev, a.d, a.k,
-                                                           a.R, a.k_r, a.valtype, a.slab);
+        k_slab_scatter<<<capped(a.nnzM), kThreads, 0, s>>>(a.keys, a.cid, a.post, a.desc, a.nnzM,
+                                                           a.nnz_dev, a.d, a.k, a.R, a.k_r,
+                                                           a.valtype, a.slab);
     return hipGetLastError();
 }
 

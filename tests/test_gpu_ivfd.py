@@ -160,3 +160,27 @@ def test_ivfd_rejects_what_it_does_not_support():
     with pytest.raises(ivf.IvfError):
         km.assign_ivfd(i32(np.full(x.n, -1, np.int32)), objects_per_range=1000)
     km.close()
+
+
+@pytest.mark.parametrize("obj_scale,mean_scale", [(50.0, 1000.0), (1.0, 1e-6), (0.02, 3.0)])
+def test_fixed_point_scale_follows_the_norms(obj_scale, mean_scale):
+    # objects and caller means of any norm: the fixed-point scale comes from
+    # the largest norms (here 2^F = 2^15, 2^51 and 2^31 -ish), so the sums
+    # neither overflow nor lose the ranking
+    x0 = datagen.generate(6000, 2500, 25.0, 1, 100, 1.1, 508)
+    x = datagen.CSR(x0.n, x0.d, x0.indptr, x0.indices,
+                    (x0.values.astype(np.float64) * obj_scale).astype(np.float32))
+    k = 40
+    m0 = oracle.initial_means(x0, datagen.seed_objects(x0, k, 508))
+    means = oracle.Means(k, x.d, m0.indptr, m0.indices, m0.values * mean_scale)
+    prev = np.full(x.n, -1, np.int32)
+    ref = oracle.ivfd_assign(x, means, prev)
+    km = ivf.IVFKMeans(*to_dev(x), x.d, k)
+    km.set_means(*means_to_dev(means))
+    g = i32(prev)
+    st = km.assign_ivfd(g, objects_per_range=4096)
+    _check_step(st, ref, g.cpu().numpy())
+    ga = i32(prev)
+    km.assign(ga)
+    assert torch.equal(g, ga)
+    km.close()

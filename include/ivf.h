@@ -296,6 +296,10 @@ const char* ivf_status_str(int32_t status);
  * Tiles: with opts->cluster_range == 0 an autotuner times the batched walk
  * over a few (clusters per tile, waves per workgroup) shapes on the means of
  * the second iteration and keeps the fastest; otherwise the given shape is used.
+ * After the walk, the instances' merges and updates run on 4 streams the
+ * batch creates (default priority), forked from and joined back into the
+ * batch stream within every iteration, so work the caller enqueues on the
+ * batch stream after a call is ordered after all of it.
  */
 typedef struct ivf_batch ivf_batch;
 

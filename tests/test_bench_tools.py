@@ -1,0 +1,101 @@
+"""The measurement helpers of bench.py on synthetic rocprofv3 output (CPU):
+the counter calibration and scaling, the kernel-trace summary, the
+algorithmic byte counts and the stale-counter rule."""
+import csv
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+WALK = "void ivf::(anonymous namespace)::k_walk<0>(ivf::WalkArgs)"
+BATCH = "void ivf::(anonymous namespace)::k_walk_batch<0>(ivf::WalkArgs const*, long const*, int, int, unsigned long long*)"
+IVFD = "void ivf::(anonymous namespace)::k_ivfd_walk<4>(ivf::IvfdArgs)"
+COPY = "__amd_rocclr_copyBuffer"
+
+
+def _write(path, fields, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def _counter_csv(path, counter, rows):
+    _write(path, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+           [{"Dispatch_Id": i, "Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v}
+            for i, (k, v) in enumerate(rows)])
+
+
+def test_counter_scaling_uses_the_copy_calibration_and_the_last_launch(tmp_path):
+    kib = bench.COPY_BYTES / 1024.0
+    # the copy reads half of its bytes by this counter and writes all of them
+    _counter_csv(tmp_path / "fetch.csv", "FETCH_SIZE",
+                 [(COPY, kib / 2), (COPY, kib / 2), (COPY, kib / 2), (BATCH, 9e9), (WALK, 1000.0),
+                  (WALK, 2000.0)])
+    _counter_csv(tmp_path / "write.csv", "WRITE_SIZE",
+                 [(COPY, kib), (COPY, kib), (COPY, kib), (WALK, 10.0), (WALK, 30.0)])
+    out = bench.summarize_counters(str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv"),
+                                   "w", "f32", str(tmp_path / "t.json"), "cmd")
+    assert out["fetch_scale"] == pytest.approx(2.0) and out["write_scale"] == pytest.approx(1.0)
+    # the last k_walk launch (not k_walk_batch, not the copies), scaled
+    assert out["fetch_bytes"] == pytest.approx(2000.0 * 1024 * 2.0)
+    assert out["write_bytes"] == pytest.approx(30.0 * 1024)
+    assert out["hbm_bytes_per_launch"] == pytest.approx(out["fetch_bytes"] + out["write_bytes"])
+    assert out["kernel_hash"] == bench.kernel_hash()
+    assert json.load(open(tmp_path / "t.json"))["hbm_bytes_per_launch"] == out["hbm_bytes_per_launch"]
+
+
+def test_counter_summary_of_the_ivfd_kernel_hashes_its_own_source(tmp_path):
+    kib = bench.COPY_BYTES / 1024.0
+    _counter_csv(tmp_path / "fetch.csv", "FETCH_SIZE", [(COPY, kib / 2)] * 3 + [(WALK, 5.0), (IVFD, 7.0)])
+    _counter_csv(tmp_path / "write.csv", "WRITE_SIZE", [(COPY, kib)] * 3 + [(IVFD, 1.0)])
+    out = bench.summarize_counters(str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv"),
+                                   "w", "f32", str(tmp_path / "t.json"), "cmd", "k_ivfd_walk")
+    assert out["fetch_bytes"] == pytest.approx(7.0 * 1024 * 2.0)
+    assert out["kernel_hash"] == bench.kernel_hash("ivfd.hip") != bench.kernel_hash()
+
+
+def test_trace_summary_lists_launches_and_the_steady_state_average(tmp_path):
+    stats = tmp_path / "x_kernel_stats.csv"
+    trace = tmp_path / "x_kernel_trace.csv"
+    _write(stats, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+           [{"Name": WALK, "Calls": 3, "TotalDurationNs": 2.5e9, "AverageNs": 8.3e8, "Percentage": 90},
+            {"Name": "ivf::(anonymous namespace)::k_merge(ivf::MergeArgs)", "Calls": 3,
+             "TotalDurationNs": 1e7, "AverageNs": 3.3e6, "Percentage": 1}])
+    launches = [(0, 500_000_000), (1_000_000_000, 1_900_000_000), (2_000_000_000, 2_910_000_000)]
+    _write(trace, ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "VGPR_Count",
+                   "Accum_VGPR_Count", "SGPR_Count", "LDS_Block_Size", "Workgroup_Size_X",
+                   "Grid_Size_X"],
+           [{"Kernel_Name": WALK, "Start_Timestamp": a, "End_Timestamp": b, "VGPR_Count": 40,
+             "Accum_VGPR_Count": 0, "SGPR_Count": 112, "LDS_Block_Size": 0,
+             "Workgroup_Size_X": 512, "Grid_Size_X": 393216} for a, b in launches])
+    out = tmp_path / "s.txt"
+    bench.summarize_trace(str(stats), str(out), "the command", "a note")
+    text = out.read_text()
+    assert "# command: the command" in text and "# a note" in text
+    assert "500.000, 900.000, 910.000" in text
+    assert "after the first" in text and "905.000 ms" in text
+    assert text.index("k_walk<0>") < text.index("k_merge")
+
+
+def test_algorithmic_bytes_and_the_stale_counter_rule(tmp_path, monkeypatch):
+    # 8 B per FP32 posting entry (id + value), 4 B for 16-bit values; 16 B per
+    # object nonzero; 8 B per row pointer
+    assert bench.walk_bytes(10, 3, 2, "f32") == 80 + 48 + 24
+    assert bench.walk_bytes(10, 3, 2, "bf16") == 40 + 48 + 24
+    assert bench.iteration_bytes(10, 3, 2, 5, "f32") == bench.walk_bytes(10, 3, 2, "f32") + 16 + 48 + 5 * 32
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles")
+    monkeypatch.setattr(bench, "kernel_hash", lambda source="assign.hip": "abc")
+    p = tmp_path / "profiles" / "walk_w_f32_traffic.json"
+    p.write_text(json.dumps({"kernel_hash": "abc", "hbm_bytes_per_launch": 123.0}))
+    assert bench.measured_traffic("w", "f32", None) == 123.0
+    p.write_text(json.dumps({"kernel_hash": "old", "hbm_bytes_per_launch": 123.0}))
+    assert bench.measured_traffic("w", "f32", None) is None      # counters of another kernel
+    assert bench.measured_traffic("w", "bf16", None) is None     # none taken

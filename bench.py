@@ -479,6 +479,8 @@ def run_batched(args):
     plan = b.plan
     tuning = b.tuning
     log("autotuner (clusters per tile, waves, walk ms): %s" % tuning)
+    thetas = b.threshold_tuning
+    log("autotuner (dense-slab threshold, walk ms): %s" % thetas)
 
     mult = sum(s["mult_adds"] for st in per for s in st)
     walk_avg_s = sum(st[0]["walk_ms"] for st in per) / len(per) / 1e3
@@ -528,7 +530,9 @@ def run_batched(args):
                    "k_range": [min(w.k for w, _ in inst), max(w.k for w, _ in inst)],
                    "valtype": args.valtype, "plan": plan,
                    "autotuner": [{"clusters_per_tile": t[0], "waves": t[1], "walk_ms": t[2]}
-                                 for t in tuning]},
+                                 for t in tuning],
+                   "autotuner_dense_threshold": [{"threshold": round(t, 4), "walk_ms": ms}
+                                                 for (t, ms) in thetas]},
         "iter_per_s": args.steps / t_total,
         "mult_adds_per_iter": mult / len(per),
         "walk_ms": 1e3 * walk_avg_s,

@@ -296,6 +296,8 @@ const char* ivf_status_str(int32_t status);
  * Tiles: with opts->cluster_range == 0 an autotuner times the batched walk
  * over a few (clusters per tile, waves per workgroup) shapes on the means of
  * the second iteration and keeps the fastest; otherwise the given shape is used.
+ * When it runs and opts->dense_threshold is 0, it then times a few dense-slab
+ * thresholds (0.35, 0.5, 0.65) on the chosen shape and keeps the fastest.
  * After the walk, the instances' merges and updates run on 4 streams the
  * batch creates (default priority), forked from and joined back into the
  * batch stream within every iteration, so work the caller enqueues on the
@@ -366,6 +368,16 @@ ivf_status ivf_batch_get_plan(const ivf_batch* b, int32_t plan[8]);
  */
 ivf_status ivf_batch_get_tuning(const ivf_batch* b, int32_t cap, int32_t* shapes, float* ms,
                                 int32_t* count);
+
+/*
+ * ivf_batch_get_threshold_tuning: the dense-slab thresholds the autotuner
+ * timed on its chosen shape (host outputs), as ivf_batch_get_tuning: *count
+ * receives how many (0 before it ran, when the shape was given or when
+ * opts->dense_threshold was set), thetas[i] the threshold, ms[i] the batched
+ * walk's device time with it; the first is the default the shapes were timed at.
+ */
+ivf_status ivf_batch_get_threshold_tuning(const ivf_batch* b, int32_t cap, float* thetas,
+                                          float* ms, int32_t* count);
 
 /* Frees the batch, its instances and its stream if it created one. */
 void ivf_batch_destroy(ivf_batch* b);

@@ -331,6 +331,17 @@ class IVFBatch:
                                                          ctypes.byref(n)), self._b)
         return [(shapes[2 * i], shapes[2 * i + 1], ms[i]) for i in range(min(n.value, cap))]
 
+    @property
+    def threshold_tuning(self):
+        """[(dense-slab threshold, walk ms)] the autotuner measured on its shape."""
+        cap = 16
+        thetas = (ctypes.c_float * cap)()
+        ms = (ctypes.c_float * cap)()
+        n = ctypes.c_int32()
+        _lib.check_batch(_lib.get().ivf_batch_get_threshold_tuning(self._b, cap, thetas, ms,
+                                                                   ctypes.byref(n)), self._b)
+        return [(thetas[i], ms[i]) for i in range(min(n.value, cap))]
+
     def close(self):
         if getattr(self, "_b", None):
             _lib.get().ivf_batch_destroy(self._b)

@@ -84,6 +84,9 @@ SIGNATURES = {
     "ivf_batch_get_plan": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "ivf_batch_get_tuning": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32),
                                        ctypes.POINTER(c_float), ctypes.POINTER(c_int32)]),
+    "ivf_batch_get_threshold_tuning": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_float),
+                                                 ctypes.POINTER(c_float),
+                                                 ctypes.POINTER(c_int32)]),
     "ivf_batch_destroy": (None, [c_void_p]),
     "ivf_batch_last_error": (ctypes.c_char_p, [c_void_p]),
 }

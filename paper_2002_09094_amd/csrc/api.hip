@@ -307,6 +307,11 @@ ivf_status read_errors(ivf_handle* h, const char* what) {
     return fail(h, IVF_ERR_NEGATIVE, m + "value <= 0");
 }
 
+// Default share of a range's clusters from which a (term, range) slice is a
+// dense slab: measured fastest at 8M documents x k = 10,000 (FP32: 936 ms
+// against 962 ms at 0.5 and 995 ms at 0.2; BF16 670 against 677 ms; FP16 flat)
+constexpr float kDenseDefault = 0.35f;
+
 IvfArgs ivf_args(ivf_handle* h, int b) {
     IvfArgs a{};
     a.d = h->d;
@@ -314,9 +319,7 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
     a.k_r = h->plan.k_r;
     a.R = h->plan.R;
     a.valtype = h->opt.valtype;
-    // 0.35 measured fastest at 8M documents x k = 10,000 (FP32: 936 ms against
-    // 962 ms at 0.5 and 995 ms at 0.2; BF16 670 against 677 ms; FP16 flat)
-    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold : 0.35f;
+    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold : kDenseDefault;
     a.mm_idx = h->mm_idx[b];
     a.mm_val = h->mm_val[b];
     a.mm_row = h->mm_row[b];
@@ -807,6 +810,8 @@ struct ivf_batch {
     int32_t captures = 0;     // times the iteration was recorded
     std::vector<float> tune_ms;   // autotuner: walk time of each candidate tried
     std::vector<int32_t> tune_shape;   // and its (clusters per tile, waves) pairs
+    std::vector<float> tune_theta;     // dense-slab thresholds tried on the chosen shape
+    std::vector<float> tune_theta_ms;  // and the walk time with each
     hipEvent_t ev[2] = {nullptr, nullptr};
     // device real-time clock read just before and just after the batched walk:
     // kernel nodes, so graph replays time the walk too
@@ -905,35 +910,63 @@ ivf_status batch_plan(ivf_batch* b, int32_t kr_max, int32_t waves) {
     return upload_args(b);
 }
 
+// Device time of one batched walk on the current plan and means.
+ivf_status time_batch_walk(ivf_batch* b, float* ms) {
+    BHIP(b, hipEventRecord(b->ev[0], b->stream));
+    BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, (int32_t)b->h.size(), b->tile_stride,
+                              b->opt.valtype, b->waves, b->grid, b->d_work, b->stream));
+    BHIP(b, hipEventRecord(b->ev[1], b->stream));
+    BHIP(b, hipEventSynchronize(b->ev[1]));
+    BHIP(b, hipEventElapsedTime(ms, b->ev[0], b->ev[1]));
+    return IVF_OK;
+}
+
 // Autotuner: time the batched walk on the current means for every candidate
-// (clusters per tile, waves per workgroup) and keep the fastest.
+// (clusters per tile, waves per workgroup) and keep the fastest; then, unless
+// the caller fixed it, the dense-slab threshold on that shape.
 ivf_status batch_autotune(ivf_batch* b) {
     // 640-wide tiles measured slowest on every mix tried; wider tiles favour
     // batches whose k spread past one 1280-wide range, 1024 the FP32 walk of
     // large k (the single-instance planner's choice)
     static const int32_t cand[][2] = {{1024, 8}, {1280, 8}, {2560, 4}, {2560, 8}, {5120, 4}};
-    const int32_t count = (int32_t)b->h.size();
     float best = 1e30f;
     int bi = 0;
     b->tune_ms.clear();
     b->tune_shape.clear();
+    b->tune_theta.clear();
+    b->tune_theta_ms.clear();
     for (int c = 0; c < (int)(sizeof(cand) / sizeof(cand[0])); ++c) {
         ivf_status st = batch_plan(b, cand[c][0], cand[c][1]);
         if (st != IVF_OK) return st;
         float ms = 0.f;
-        BHIP(b, hipEventRecord(b->ev[0], b->stream));
-        BHIP(b, launch_walk_batch(b->d_args, b->d_item_off, count, b->tile_stride,
-                                  b->opt.valtype, b->waves, b->grid, b->d_work,
-                                  b->stream));
-        BHIP(b, hipEventRecord(b->ev[1], b->stream));
-        BHIP(b, hipEventSynchronize(b->ev[1]));
-        BHIP(b, hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+        st = time_batch_walk(b, &ms);
+        if (st != IVF_OK) return st;
         b->tune_ms.push_back(ms);
         b->tune_shape.push_back(cand[c][0]);
         b->tune_shape.push_back(cand[c][1]);
         if (ms < best) { best = ms; bi = c; }
     }
     b->tuned = true;
+    if (b->opt.dense_threshold > 0.f) return batch_plan(b, cand[bi][0], cand[bi][1]);
+    // A higher threshold stores fewer, fuller slabs: fewer zero bytes read,
+    // more (id, value) entries.  Mixes of many small instances measured
+    // fastest above the default chosen for one large instance.
+    static const float thetas[] = {0.5f, 0.65f};
+    float t_best = kDenseDefault;
+    b->tune_theta.push_back(kDenseDefault);
+    b->tune_theta_ms.push_back(best);
+    for (float t : thetas) {
+        for (ivf_handle* h : b->h) h->opt.dense_threshold = t;
+        ivf_status st = batch_plan(b, cand[bi][0], cand[bi][1]);
+        if (st != IVF_OK) return st;
+        float ms = 0.f;
+        st = time_batch_walk(b, &ms);
+        if (st != IVF_OK) return st;
+        b->tune_theta.push_back(t);
+        b->tune_theta_ms.push_back(ms);
+        if (ms < best) { best = ms; t_best = t; }
+    }
+    for (ivf_handle* h : b->h) h->opt.dense_threshold = t_best;
     return batch_plan(b, cand[bi][0], cand[bi][1]);
 }
 
@@ -1597,6 +1630,18 @@ ivf_status ivf_batch_get_tuning(const ivf_batch* b, int32_t cap, int32_t* shapes
         shapes[2 * i] = b->tune_shape[2 * i];
         shapes[2 * i + 1] = b->tune_shape[2 * i + 1];
         ms[i] = b->tune_ms[i];
+    }
+    return IVF_OK;
+}
+
+ivf_status ivf_batch_get_threshold_tuning(const ivf_batch* b, int32_t cap, float* thetas,
+                                          float* ms, int32_t* count) {
+    if (!b || !count || cap < 0 || (cap > 0 && (!thetas || !ms))) return IVF_ERR_ARG;
+    const int32_t n = (int32_t)b->tune_theta.size();
+    *count = n;
+    for (int32_t i = 0; i < n && i < cap; ++i) {
+        thetas[i] = b->tune_theta[i];
+        ms[i] = b->tune_theta_ms[i];
     }
     return IVF_OK;
 }

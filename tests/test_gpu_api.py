@@ -149,10 +149,28 @@ def test_batch_multi_iteration_calls_and_tuning_report():
     tuning = b.tuning
     assert len(tuning) == 5 and all(ms > 0 for (_, _, ms) in tuning)
     assert b.plan["kr_max"] == min(tuning, key=lambda t: t[2])[0]
+    # then the dense-slab threshold on that shape, the default first
+    thetas = b.threshold_tuning
+    assert [round(t, 6) for (t, _) in thetas] == [0.35, 0.5, 0.65]
+    assert all(ms > 0 for (_, ms) in thetas)
+    assert thetas[0][1] == min(ms for (_, _, ms) in tuning)
     for i, (x, _, _, _, seeds) in enumerate(inst):
         ref = list(oracle.chain(x, seeds, 6))
         assert np.array_equal(ba[i].cpu().numpy(), ref[-1].assign.assign)
         assert [s[i]["changed"] for s in stats] == [r.assign.changed for r in ref]
+    b.close()
+
+
+def test_batch_threshold_given_by_the_caller_is_not_tuned():
+    x = datagen.generate(1500, 900, 15.0, 1, 60, 1.15, 409)
+    k = 60
+    b = ivf.IVFBatch([(*to_dev(x), 900)], [k], dense_threshold=0.2)
+    b.init_seeds([i32(datagen.seed_objects(x, k, 409))])
+    a = [i32(np.full(x.n, -1, np.int32))]
+    b.iterate(3, a)
+    assert len(b.tuning) == 5 and b.threshold_tuning == []
+    ref = list(oracle.chain(x, datagen.seed_objects(x, k, 409), 3))
+    assert np.array_equal(a[0].cpu().numpy(), ref[-1].assign.assign)
     b.close()
 
 

@@ -318,9 +318,10 @@ __device__ inline int64_t claim_item(unsigned long long* ctr, int lane) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Waves per SIMD the walk is compiled for (the register budget): 16-bit
-// values fit 8 without spilling; the FP32 walk keeps 6 (more waves measured no
-// faster: it is bound by L2 capacity, not by latency hiding).
+// Waves per SIMD the walk is compiled for (the register budget): 8 for 16-bit
+// values (about ten registers spill; 7, without spills, measured 2 % slower);
+// the FP32 walk keeps 6 (8 measured 18 % slower: it is bound by L2 capacity,
+// not by latency hiding).
 template <int VT>
 __global__ __launch_bounds__(kWave * kMaxWaves)
 __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(WalkArgs a) {
@@ -329,25 +330,17 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(W
     // wave index made provably uniform, so every loop below has uniform bounds
     // and cross-lane reads always see all 64 lanes active
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
     float* tile = reinterpret_cast<float*>(lds4) + (int64_t)wv * a.tile_stride;
     zero_tile(tile, a.tile_stride, lane);
     const int64_t total = a.items_per_range * a.R;
-    // items in ascending order: all waves sweep the ranges in the same order,
-    // so a range's slices stay hot in the caches
-    if constexpr (VT == IVF_VAL_F32) {
-        // claimed from the counter: keeps the waves in one window of items
-        // (2 % faster than the round robin at 8M documents x k = 10,000)
-        for (;;) {
-            const int64_t w = claim_item(&a.cnt->work, lane);
-            if (w >= total) break;
-            walk_item<VT, true>(a, w, tile, lane);
-        }
-    } else {
-        // static round robin: at 8 waves per SIMD the claim would spill
-        // registers (16-bit walks measured 19 % slower with it)
-        for (int64_t w = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv; w < total; w += nwaves)
-            walk_item<VT>(a, w, tile, lane);
+    // items in ascending order, claimed from the counter: all waves sweep the
+    // ranges in the same order and stay within one window of consecutive
+    // items, so a range's slices stay hot in the caches (against a static
+    // round robin at 8M documents x k = 10,000: FP32 2 % faster, 16-bit 14 %)
+    for (;;) {
+        const int64_t w = claim_item(&a.cnt->work, lane);
+        if (w >= total) break;
+        walk_item<VT, VT == IVF_VAL_F32>(a, w, tile, lane);
     }
 }
 

@@ -51,9 +51,11 @@ def iteration_bytes(m, nnz, n, nnz_means, valtype):
             + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
 
 
-def kernel_hash(source="assign.hip"):
+def kernel_hash(sources=("assign.hip", "update.hip")):
+    """Hash of a kernel's sources and the shared headers: the walk's kernels
+    and the inverted-file layout they read (slabs, postings) by default."""
     h = hashlib.sha256()
-    for f in (source, "kernels.h", "ivf_internal.h"):
+    for f in (*sources, "kernels.h", "ivf_internal.h"):
         with open(os.path.join(ROOT, "paper_2002_09094_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -221,7 +223,7 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         f.write("\n".join(lines) + "\n")
 
 
-KERNEL_SOURCE = {"k_walk": "assign.hip", "k_ivfd_walk": "ivfd.hip"}
+KERNEL_SOURCE = {"k_walk": ("assign.hip", "update.hip"), "k_ivfd_walk": ("ivfd.hip",)}
 
 
 def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, command,

@@ -58,7 +58,7 @@ def test_counter_summary_of_the_ivfd_kernel_hashes_its_own_source(tmp_path):
     out = bench.summarize_counters(str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv"),
                                    "w", "f32", str(tmp_path / "t.json"), "cmd", "k_ivfd_walk")
     assert out["fetch_bytes"] == pytest.approx(7.0 * 1024 * 2.0)
-    assert out["kernel_hash"] == bench.kernel_hash("ivfd.hip") != bench.kernel_hash()
+    assert out["kernel_hash"] == bench.kernel_hash(("ivfd.hip",)) != bench.kernel_hash()
 
 
 def test_trace_summary_lists_launches_and_the_steady_state_average(tmp_path):
@@ -92,7 +92,7 @@ def test_algorithmic_bytes_and_the_stale_counter_rule(tmp_path, monkeypatch):
     assert bench.iteration_bytes(10, 3, 2, 5, "f32") == bench.walk_bytes(10, 3, 2, "f32") + 16 + 48 + 5 * 32
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "profiles")
-    monkeypatch.setattr(bench, "kernel_hash", lambda source="assign.hip": "abc")
+    monkeypatch.setattr(bench, "kernel_hash", lambda sources=("assign.hip", "update.hip"): "abc")
     p = tmp_path / "profiles" / "walk_w_f32_traffic.json"
     p.write_text(json.dumps({"kernel_hash": "abc", "hbm_bytes_per_launch": 123.0}))
     assert bench.measured_traffic("w", "f32", None) == 123.0

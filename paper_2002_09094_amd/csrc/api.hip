@@ -460,6 +460,7 @@ ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0,
         r.mm_ptr = h->mm_ptr[h->cur]; r.mm_idx = h->mm_idx[h->cur]; r.mm_val = h->mm_val[h->cur];
         r.valtype = h->opt.valtype;
         r.fixed_scale = fixed_scale;
+        r.rec = rec ? nullptr : h->rec;   // another walk's records bound other ranges
         r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
         r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
         HIPCHK(h, launch_rescore(r, h->rescore_waves, h->rescore_grid, s));

@@ -525,13 +525,19 @@ __device__ inline double exact_score(const RescoreArgs& a, int64_t hb, int64_t h
     return sum;
 }
 
-// Objects the FP32 bound could not certify, one per wave.  The wave walks the
-// object again in FP32 (the same code, so the tile holds the scores the walk
-// had).  A cluster j is a candidate unless the bounds prove it below the
-// FP32 winner (each score within its own walk's bound of the FP64 one): every non-candidate's FP64 score is then strictly smaller than
-// the winner's, so the FP64 argmax (lowest j on equal scores) is among the
-// candidates.  Candidates get their exact FP64 score and, in ascending j with
-// a strict test from 0, the reference's rule picks the cluster.
+// Objects the FP32 bound could not certify, one per wave.  A cluster j is a
+// candidate unless the bounds prove it below the FP32 winner (each score
+// within its own walk's bound of the FP64 one): every non-candidate's FP64
+// score is then strictly smaller than the winner's, so the FP64 argmax
+// (lowest j on equal scores) is among the candidates.  Candidates get their
+// exact FP64 score and, in ascending j with a strict test from 0, the
+// reference's rule picks the cluster.
+// The walk's record of each range bounds its scores: its best is the range
+// winner's, its second the largest of every other cluster's.  A range whose
+// best cannot be a candidate is skipped; one whose second cannot be holds one
+// candidate, its winner; any other range is walked again in FP32 (the same
+// code, so the tile holds the scores the walk had) and its candidates read
+// from the tile.  Without records (another walk's), every range is walked.
 template <int VT>
 __global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
     extern __shared__ float4 lds4[];
@@ -565,6 +571,19 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
         for (int r = 0; r < w.R; ++r) {
             const int32_t base = r * w.k_r;
             const int32_t kr = min(w.k_r, w.k - base);
+            if (a.rec) {
+                const RangeRec rr = a.rec[i * w.R + r];
+                if (cert_ub((double)rr.best, c, ab, g) < thr) continue;
+                if (rr.id >= 0 && cert_ub((double)rr.second, c, ab, g) < thr) {
+                    const double e = exact_score(a, hb, he, rr.id, lane);
+                    if (e > best) {
+                        best = e;
+                        bj = rr.id;
+                    }
+                    if (rr.id == fw) rho_fw = e;
+                    continue;
+                }
+            }
             accumulate_object<VT>(w, i, r, base, kr, tile, lane);
             for (int s0 = 0; s0 < kr; s0 += 4 * kWave) {
                 const int s = s0 + 4 * lane;

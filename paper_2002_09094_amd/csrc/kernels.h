@@ -44,6 +44,7 @@ struct RescoreArgs {
     const double* mm_val;
     int32_t valtype;
     double fixed_scale;       // > 0: `best` is a fixed-point sum (IVFD) of this scale
+    const RangeRec* rec;      // the walk's range records, [n * w.R] (null: re-walk every range)
     const int32_t* rescore_list;
     const int32_t* prev;
     int32_t* assign;

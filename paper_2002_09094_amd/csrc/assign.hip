@@ -444,6 +444,8 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 7, 8))) void k_walk_b
 __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t m = 0;
+    bool zero = false, cert = false;
+    double rel = 0.0;   // the certified winner's relative bound (>= 0)
     if (i < a.n) {
         float b = 0.f, s2 = 0.f;
         int32_t id = -1;
@@ -468,7 +470,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
             a.assign[i] = prev;
             a.rho[i] = 0.0;
             flag = 4;
-            atomicAdd(&a.cnt->zero_overlap, 1ull);
+            zero = true;
         } else {
             double c, ab, g;
             if (a.fixed_scale > 0.0)
@@ -481,9 +483,8 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
                 a.assign[i] = id >= 0 ? id : prev;
                 a.rho[i] = (double)b;
                 flag = ok ? 1 : 0;
-                if (ok) atomicAdd(&a.cnt->certified, 1ull);
-                const double rel = c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0);
-                atomicMax(&a.cnt->max_bound_bits, (unsigned long long)__double_as_longlong(rel));
+                cert = ok;
+                rel = c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0);
             } else {
                 const unsigned long long slot = atomicAdd(&a.cnt->n_rescore, 1ull);
                 a.rescore_list[slot] = (int32_t)i;
@@ -492,10 +493,24 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
         }
         a.flags[i] = flag;
     }
-    // the entries walked (M), summed per wave: one atomic per wave
+    // the entries walked (M), the certified and zero-overlap counts and the
+    // largest bound, reduced per wave: one atomic per wave and counter rather
+    // than one per object on a single address (non-negative doubles order
+    // like their bit patterns)
 #pragma unroll
-    for (int o = kWave / 2; o >= 1; o >>= 1) m += __shfl_xor(m, o, kWave);
-    if (lane_id() == 0 && m) atomicAdd(&a.cnt->mult, (unsigned long long)m);
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        m += __shfl_xor(m, o, kWave);
+        rel = fmax(rel, __shfl_xor(rel, o, kWave));
+    }
+    const unsigned long long n_cert = __popcll(__ballot(cert));
+    const unsigned long long n_zero = __popcll(__ballot(zero));
+    if (lane_id() == 0) {
+        if (m) atomicAdd(&a.cnt->mult, (unsigned long long)m);
+        if (n_cert) atomicAdd(&a.cnt->certified, n_cert);
+        if (n_zero) atomicAdd(&a.cnt->zero_overlap, n_zero);
+        if (rel > 0.0)
+            atomicMax(&a.cnt->max_bound_bits, (unsigned long long)__double_as_longlong(rel));
+    }
 }
 
 // FP64 score of cluster j for the object with nonzeros [hb, he), exactly as

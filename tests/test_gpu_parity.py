@@ -94,6 +94,30 @@ def test_chain_parity_gpu_means(name):
     km.close()
 
 
+@pytest.mark.parametrize("valtype", ["f32", "bf16", "f16"])
+def test_wide_ranges_parity(valtype):
+    """Ranges wider than one round trip's slab (two ranges of 1,300 and 1,299
+    clusters under a 2,048 limit): dense slabs take the looped path and 16-bit
+    terms are not paired; assignments, M and the zero-overlap count equal the
+    oracle's."""
+    n, d, k, seed = 3000, 1500, 2599, 107
+    x = datagen.generate(n, d, 40.0, 2, 150, 1.1, seed)
+    seeds = datagen.seed_objects(x, k, seed)
+    print("wide ranges", valtype, "n", n, "k", k, "nnz", x.nnz, flush=True)
+    km = ivf.IVFKMeans(*to_dev(x), d, k, valtype=valtype, cluster_range=2048)
+    assert km.plan["k_r"] == 1300 and km.plan["ranges"] == 2
+    last = np.full(n, -1, np.int32)
+    for r, st in enumerate(oracle.chain(x, seeds, 3)):
+        km.set_means(*means_to_dev(st.means_in))
+        a = i32(last)
+        gs = km.assign(a)
+        assert np.array_equal(a.cpu().numpy(), st.assign.assign), (valtype, r)
+        assert gs["mult_adds"] == st.assign.mult_adds
+        assert gs["zero_overlap"] == st.assign.zero_overlap
+        last = st.assign.assign
+    km.close()
+
+
 @pytest.mark.parametrize("valtype", ["bf16", "f16"])
 def test_half_precision_values_same_assignments(valtype):
     n, d, lam, lo, hi, s, k, seed, opts = _case("k300_ranges")

@@ -52,8 +52,10 @@ typedef enum {
 } ivf_status;
 
 /* Precision of the mean values stored in the inverted file used by the
- * assignment walk.  Scores are always accumulated in FP32; objects whose
- * top-1/top-2 margin is inside the stated error bound are re-scored in FP64. */
+ * assignment walk.  Scores are always accumulated in FP32 (a rounded product
+ * then a rounded sum for FP32 values, one fused multiply-add for 16-bit ones;
+ * the stated bound covers both); objects whose top-1/top-2 margin is inside
+ * that error bound are re-scored in FP64. */
 typedef enum { IVF_VAL_F32 = 0, IVF_VAL_BF16 = 1, IVF_VAL_F16 = 2 } ivf_valtype;
 
 /* Object set, CSR (the paper's sparse expression of Fig. "fig:str"(a)).

@@ -36,18 +36,20 @@ def log(msg):
 T0 = time.perf_counter()
 
 
-def walk_bytes(m, nnz, n, valtype):
+def walk_bytes(m, nnz, n, ranges, valtype):
     """Algorithmic bytes of one walk launch: every posting entry walked (cluster
-    id + value), each object nonzero (term id + value) with its list bounds
-    (two int32), the object row pointers."""
-    return ENTRY_BYTES[valtype] * m + 16 * nnz + 8 * (n + 1)
+    id + value: 8 B for FP32 values, 4 B for 16-bit local ids and values);
+    per cluster range, each object nonzero (term id + value, 8 B) with its
+    slice descriptor (two int64, 16 B), the object row pointers (8 B) and the
+    object's range record written (16 B)."""
+    return ENTRY_BYTES[valtype] * m + ranges * (24 * nnz + 8 * (n + 1) + 16 * n)
 
 
-def iteration_bytes(m, nnz, n, nnz_means, valtype):
+def iteration_bytes(m, nnz, n, ranges, nnz_means, valtype):
     """Algorithmic bytes of one Lloyd iteration: the walk, the assignment
     read/write, and the update (the object entries grouped by cluster: key,
     position, term, value; FP64 mean entries written; inverted file written)."""
-    return (walk_bytes(m, nnz, n, valtype) + 8 * n + 16 * nnz
+    return (walk_bytes(m, nnz, n, ranges, valtype) + 8 * n + 16 * nnz
             + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
 
 
@@ -61,61 +63,185 @@ def kernel_hash(sources=("assign.hip", "update.hip")):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, valtype, n_launch_units):
-    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "walk_%s_%s_traffic.json" % (workload, valtype))
+# Working sets of the read-ceiling probes: (bytes, mode, passes).  mode 0:
+# every workgroup reads the whole buffer (resident in each XCD's L2); mode 1:
+# the buffer split among the workgroups and swept `passes` times (128 MiB:
+# beyond the L2s, inside the 256 MB Infinity Cache; 4 GiB: HBM).
+CEILINGS = {"l2": (2 << 20, 0, 40), "infinity_cache": (128 << 20, 1, 100),
+            "hbm": (4 << 30, 1, 3)}
+PROBE_WORKGROUPS_PER_CU = 8
+
+
+def probe_bytes(level, cus):
+    """Bytes one timed probe launch reads at `level`."""
+    nbytes, mode, passes = CEILINGS[level]
+    n16 = nbytes // 16
+    if mode == 0:
+        return cus * PROBE_WORKGROUPS_PER_CU * n16 * 16 * passes
+    return n16 * 16 * passes
+
+
+def read_ceilings():
+    """Measured read bandwidth (GB/s) of working sets resident in L2, in the
+    Infinity Cache and in HBM: the roofs the walk's counted traffic is placed
+    against (the library's streaming read probe, one warm-up and one timed
+    launch each)."""
+    import torch
+
+    import paper_2002_09094_amd as ivf
+
+    out = {}
+    for level, (nbytes, mode, passes) in CEILINGS.items():
+        buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        out[level] = ivf.read_ceiling(buf, mode, passes)
+        del buf
+    torch.cuda.empty_cache()
+    log("read ceilings (GB/s): " + ", ".join("%s %.0f" % kv for kv in out.items()))
+    return out
+
+
+def level_counters(kernel, workload, valtype):
+    """Per-launch bytes of the walk at each level of the memory hierarchy,
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_levels.json"
+                        % (kernel.replace("k_", ""), workload, valtype))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_hash") != kernel_hash():
+    if t.get("kernel_hash") != kernel_hash(KERNEL_SOURCE[kernel]):
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t
 
 
-def cpu_baseline(x, k, seed, target_s):
-    """The FP64 oracle timed on this host's cores on a bounded sample: means of a
-    seeded random partition (the shape of steady-state means on structureless
-    data), the assignment walk of the first S objects, scaled to the full set
-    by the exact mult-add count."""
+def walk_roofline(kernel, workload, valtype, walk_s, alg_bytes, ceilings, copy_gbps, add_gbps):
+    """The walk against the roof it hits.  The method's algorithmic bytes
+    charge every posting read to memory (the paper's per-access model), but
+    the caches serve most of them, so those bytes per second are reported as
+    an effective rate only.  The roof is set from counters: the bytes the
+    walk moved from L2 into the compute units (L1 -> L2 read requests) and
+    from the memory side into L2 (L2 -> fabric read requests, Infinity-Cache
+    hits included), each against the read ceiling measured in this run for a
+    working set resident at that level; the bound is the level with the
+    larger fraction.  The fabric bytes against the published 8 TB/s are an
+    upper bound of the walk's HBM share."""
+    out = {"kernel": kernel, "unit": "GB/s",
+           "algorithmic_bytes_per_launch": alg_bytes,
+           "effective_gbps_algorithmic": alg_bytes / walk_s / 1e9,
+           "ceilings_gbps": ceilings, "hbm_peak_published_gbps": HBM_PEAK_GBPS,
+           "stream_copy_gbps": copy_gbps, "stream_add_gbps": add_gbps}
+    lv = level_counters(kernel, workload, valtype)
+    if lv is None:
+        out.update({"bound": None, "achieved": None, "peak": None, "frac": None,
+                    "traffic": None,
+                    "note": "no counter summary taken on the current kernel source"})
+        return out
+    levels = {
+        "l2": (lv["l2_read_bytes"] / walk_s / 1e9, ceilings["l2"]),
+        "infinity_cache": (lv["fabric_read_bytes"] / walk_s / 1e9, ceilings["infinity_cache"]),
+    }
+    fr = {k: a / p for k, (a, p) in levels.items()}
+    bound = max(fr, key=fr.get)
+    a, p = levels[bound]
+    out.update({
+        "bound": bound, "achieved": a, "peak": p, "frac": a / p,
+        "peak_kind": "measured read ceiling of a working set resident at that level",
+        "traffic": lv["fabric_read_bytes"] + lv.get("write_bytes", 0.0),
+        "traffic_unit": "bytes per launch between L2 and the memory side (reads + writes)",
+        "levels": {k: {"achieved": a_, "peak": p_, "frac": a_ / p_}
+                   for k, (a_, p_) in levels.items()},
+        "hbm_upper_bound": {"achieved": lv["fabric_read_bytes"] / walk_s / 1e9,
+                            "peak": HBM_PEAK_GBPS,
+                            "frac": lv["fabric_read_bytes"] / walk_s / 1e9 / HBM_PEAK_GBPS},
+        "l2_hit_rate": lv.get("l2_hit_rate"),
+        "mfma_instructions": lv.get("mfma_instructions"),
+        "counters_source": lv.get("source")})
+    return out
+
+
+def cpu_baseline(x, w, valtype, check, target_s):
+    """The FP64 oracle on this host's cores, on a bounded sample of the state
+    the GPU assigned outside the timed region (the chain's means after the
+    timed iterations and its previous assignment): the oracle's assignment
+    walk over a seeded sample of S objects, S grown until the walk takes
+    about target_s / 2, scaled to the whole set by the exact mult-add count;
+    plus its update step over the whole set.  The same oracle results check
+    the GPU on the sample: identical assignments, and the largest relative
+    error of the FP32 tile scores (top-1: the tile's winner against that
+    cluster's FP64 score; top-2: the tile's best other score against the
+    oracle's, where the two winners agree)."""
     import numpy as np
 
     import datagen
     import oracle
+    import paper_2002_09094_amd as ivf
 
     cores = len(os.sched_getaffinity(0))
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    labels = datagen.uniform_labels(x.n, k, seed, stream=11)
-    log("cpu baseline: oracle update of a random partition (k=%d)" % k)
-    means, _ = oracle.update(x, k, labels, None, threads=threads)
-    no, nc = oracle.term_counts(x, means)
-    m_full = int(np.sum(no * nc))
-    s = min(x.n, 2000)
+    ptr, idx, val = check["means"]
+    means = oracle.Means(w.k, w.d, ptr, idx, val)
+    prev, got = check["prev"], check["assign"]
+    m_full = int(check["stats"]["mult_adds"])
+    s = min(x.n, 20_000)
     while True:
-        xs = x.subset(np.arange(s))
+        samp = np.sort(datagen.perm_prefix(x.n, s, w.seed, stream=23))
+        xs = x.subset(samp)
         t = time.perf_counter()
-        r = oracle.assign(xs, means, np.full(s, -1, np.int32), threads=threads)
+        r = oracle.assign(xs, means, prev[samp], threads=threads)
         dt = time.perf_counter() - t
-        log("cpu baseline: %d objects, %.3e mult-adds in %.2fs" % (s, r.mult_adds, dt))
+        log("cpu baseline: oracle walk of %d objects, %.3e mult-adds in %.2fs" % (s, r.mult_adds, dt))
         if dt >= 0.5 * target_s or s >= x.n:
             break
-        s = int(min(x.n, max(2 * s, s * target_s / max(dt, 1e-3))))
+        s = int(min(x.n, max(2 * s, s * 0.5 * target_s / max(dt, 1e-3))))
     rate = r.mult_adds / dt
-    out = {
-        "value": rate / m_full,
+    t = time.perf_counter()
+    oracle.update(x, w.k, got, means, threads=threads)
+    t_update = time.perf_counter() - t
+    log("cpu baseline: oracle update of all %d objects in %.2fs" % (x.n, t_update))
+    t_iter = m_full / rate + t_update
+    base = {
+        "value": 1.0 / t_iter,
         "unit": "iter/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": ("FP64 oracle assignment walk of the first %d of %d objects against "
-                   "means of a seeded random partition (k=%d), %.1fs; scaled by the full "
-                   "set's exact mult-add count %d" % (s, x.n, k, dt, m_full)),
-        "mult_adds_per_s": rate,
+        "sample": ("FP64 oracle on the GPU chain's state after the timed iterations: its "
+                   "assignment walk over a seeded sample of %d of %d objects (%.1fs, scaled to "
+                   "the whole set by the exact mult-add count %d) plus its update of all "
+                   "objects (%.1fs)" % (s, x.n, dt, m_full, t_update)),
+        "assign_mult_adds_per_s": rate,
+        "update_s": t_update,
         "cpu_model": cpu_model(),
         "nproc": os.cpu_count(),
     }
-    out.update(single_core_small())
-    return out
+    base.update(single_core_small())
+    # the GPU on the same sample
+    gs = got[samp]
+    best, bid, sec = (check[k][samp] for k in ("best", "best_id", "second"))
+    same = (bid == r.assign) & (r.rho > 0)
+    e1 = np.abs(best[same].astype(np.float64) - r.rho[same]) / r.rho[same]
+    other = np.nonzero((bid >= 0) & ~same)[0]
+    if len(other):   # FP32 winners the FP64 re-score overturned: their own FP64 scores
+        r64 = oracle.scores(x, means, samp[other], bid[other])
+        e1 = np.concatenate([e1, np.abs(best[other].astype(np.float64) - r64) / r64])
+    two = same & (r.rho2 > 0)
+    e2 = np.abs(sec[two].astype(np.float64) - r.rho2[two]) / r.rho2[two]
+    nmax = int(np.max(np.diff(x.indptr)))
+    c, a, g = ivf.cert_bound(valtype, nmax, float(x.values.max()))
+    st = check["stats"]
+    prec = {"sample_objects": int(s), "identical": int(np.sum(gs == r.assign)),
+            "max_rel_err_top1": float(e1.max()) if len(e1) else 0.0,
+            "max_rel_err_top2": float(e2.max()) if len(e2) else 0.0,
+            "top1_pairs": int(len(e1)), "top2_pairs": int(two.sum()),
+            "bound_c_longest_row": c,
+            "certified_fraction": st["certified"] / x.n, "rescored": st["rescored"],
+            "sample_rescored": int(np.sum(check["flags"][samp] & 2)),
+            "max_rel_err_rescored": st["max_rel_err_rescored"]}
+    log("precision check: %d of %d sampled objects identical to the oracle; max rel err "
+        "top-1 %.3g, top-2 %.3g" % (prec["identical"], s, prec["max_rel_err_top1"],
+                                    prec["max_rel_err_top2"]))
+    return base, prec
 
 
 def cpu_model():
@@ -223,7 +349,89 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         f.write("\n".join(lines) + "\n")
 
 
-KERNEL_SOURCE = {"k_walk": ("assign.hip", "update.hip"), "k_ivfd_walk": ("ivfd.hip",)}
+KERNEL_SOURCE = {"k_walk": ("assign.hip", "update.hip"), "k_walk_batch": ("assign.hip", "update.hip"),
+                 "k_ivfd_walk": ("ivfd.hip",)}
+
+
+def _last_dispatch_values(rows, match):
+    """Counter values of the last dispatch whose kernel name contains `match`."""
+    sel = [r for r in rows if match(r["Kernel_Name"])]
+    if not sel:
+        return {}
+    last = max(int(r["Dispatch_Id"]) for r in sel)
+    return {r["Counter_Name"]: float(r["Counter_Value"]) for r in sel
+            if int(r["Dispatch_Id"]) == last}
+
+
+def summarize_levels(workload, valtype, out_json, out_txt, command, kernel, cus, *csvs):
+    """Bytes the walk moved at each level of the memory hierarchy, from
+    rocprofv3 --pmc passes over a run that first times the read probes (three
+    levels, a warm-up and a timed launch each, in the order of CEILINGS) and
+    then the walk: L1 -> L2 read requests (TCP_TCC_READ_REQ_sum) and L2 ->
+    fabric read requests (TCC_EA0_RDREQ_sum) of the last walk launch, each
+    scaled to bytes by what the same counter reads for the timed probe of
+    known size (the L2-resident probe and the HBM-resident one)."""
+    import collections
+    rows = []
+    for path in csvs:
+        rows += _csv_rows(path)
+    probes = collections.OrderedDict()
+    for r in rows:
+        if "k_read" in r["Kernel_Name"]:
+            probes.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    # per counter: the probe dispatches that carry it, in order (each pass has its own ids)
+    by_counter = collections.defaultdict(list)
+    for did in sorted(probes):
+        for name, v in probes[did].items():
+            by_counter[name].append(v)
+    levels = list(CEILINGS)
+
+    def timed_probe(counter, level):
+        vals = by_counter[counter]
+        return vals[2 * levels.index(level) + 1]
+
+    walk = {}
+    for path in csvs:
+        walk.update(_last_dispatch_values(_csv_rows(path),
+                                          lambda n: ("::%s<" % kernel) in n))
+    l2_bpr = probe_bytes("l2", cus) / timed_probe("TCP_TCC_READ_REQ_sum", "l2")
+    fab_bpr = probe_bytes("hbm", cus) / timed_probe("TCC_EA0_RDREQ_sum", "hbm")
+    out = {"kernel": kernel, "workload": workload, "valtype": valtype,
+           "kernel_hash": kernel_hash(KERNEL_SOURCE[kernel]),
+           "l2_bytes_per_request": l2_bpr, "fabric_bytes_per_request": fab_bpr,
+           "l2_read_bytes": walk["TCP_TCC_READ_REQ_sum"] * l2_bpr,
+           "fabric_read_bytes": walk["TCC_EA0_RDREQ_sum"] * fab_bpr,
+           "counters": walk, "probe_counters": {k: v for k, v in by_counter.items()},
+           "source": os.path.basename(out_txt), "command": command}
+    if "TCC_HIT_sum" in walk and "TCC_MISS_sum" in walk:
+        h, m = walk["TCC_HIT_sum"], walk["TCC_MISS_sum"]
+        out["l2_hit_rate"] = h / (h + m)
+    if "TCC_EA0_WRREQ_sum" in walk:
+        out["write_bytes"] = walk["TCC_EA0_WRREQ_sum"] * fab_bpr
+    mf = [v for k, v in walk.items() if "MFMA" in k]
+    out["mfma_instructions"] = sum(mf) if mf else None
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+    lines = ["# rocprofv3 counters of the steady-state %s launch and of the read probes" % kernel,
+             "# command: " + command, "",
+             "walk counters (last dispatch):"]
+    lines += ["  %-34s %.4e" % kv for kv in walk.items()]
+    lines += ["", "probe counters (warm-up, timed) x (%s):" % ", ".join(levels)]
+    lines += ["  %-34s %s" % (k, ", ".join("%.4e" % x for x in v)) for k, v in by_counter.items()]
+    lines += ["",
+              "bytes per L1->L2 read request (L2 probe: %.4e B read): %.1f"
+              % (probe_bytes("l2", cus), l2_bpr),
+              "bytes per L2->fabric read request (HBM probe: %.4e B read): %.1f"
+              % (probe_bytes("hbm", cus), fab_bpr),
+              "walk: L2 -> CU read bytes per launch %.4e" % out["l2_read_bytes"],
+              "walk: memory side -> L2 read bytes per launch %.4e" % out["fabric_read_bytes"]]
+    if "l2_hit_rate" in out:
+        lines.append("walk: L2 hit rate (requests) %.3f" % out["l2_hit_rate"])
+    if out["mfma_instructions"] is not None:
+        lines.append("walk: MFMA instructions %d" % out["mfma_instructions"])
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return out
 
 
 def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, command,
@@ -486,34 +694,19 @@ def run_batched(args):
 
     mult = sum(s["mult_adds"] for st in per for s in st)
     walk_avg_s = sum(st[0]["walk_ms"] for st in per) / len(per) / 1e3
-    wb = [sum(walk_bytes(s["mult_adds"], data[w.name][0].nnz, w.n, args.valtype)
+    kr = plan["kr_max"]
+    wb = [sum(walk_bytes(s["mult_adds"], data[w.name][0].nnz, w.n, -(-w.k // kr), args.valtype)
               for s, (w, _) in zip(st, inst)) for st in per]
-    achieved = (sum(wb) / len(wb)) / walk_avg_s / 1e9
+    ceilings = read_ceilings()
 
-    # per-instance exactness, outside the timed region: one more iteration,
-    # a seeded sample of every instance re-assigned by the FP64 oracle from
-    # the same means and previous assignment
-    import oracle
+    # the state after the timed iterations, for the oracle leg: every
+    # instance's means and assignment, then one more iteration
     before = []
     for i, (w, _) in enumerate(inst):
         ptr, idx, val = (t.cpu().numpy() for t in b.get_means(i))
-        before.append((oracle.Means(w.k, w.d, ptr, idx, val), assigns[i].cpu().numpy()))
+        before.append(((ptr, idx, val), assigns[i].cpu().numpy()))
     b.iterate(1, assigns)
-    exact, sampled = 0, 0
-    t_or = time.perf_counter()
-    or_mult = 0
-    for i, (w, r) in enumerate(inst):
-        x = data[w.name][0]
-        m = min(w.n, 96)
-        rows = np.sort(datagen.perm_prefix(w.n, m, w.seed + 1000 * r, stream=7))
-        ar = oracle.assign(x.subset(rows), before[i][0], before[i][1][rows])
-        got = assigns[i].cpu().numpy()[rows]
-        exact += int(np.array_equal(got, ar.assign))
-        sampled += m
-        or_mult += ar.mult_adds
-    t_or = time.perf_counter() - t_or
-    log("oracle check: %d of %d instances identical on %d sampled objects (%.1fs)"
-        % (exact, len(inst), sampled, t_or))
+    after = [t.cpu().numpy() for t in assigns]
     out = {
         "metric": BATCH_METRIC,
         "value": mult / t_total,
@@ -539,50 +732,62 @@ def run_batched(args):
         "mult_adds_per_iter": mult / len(per),
         "walk_ms": 1e3 * walk_avg_s,
         "iteration_ms": sum(st[0]["assign_ms"] for st in per) / len(per),
-        "instances_identical_to_oracle": exact,
-        "oracle_sampled_objects": sampled,
         "certified_fraction": (sum(s["certified"] for st in per for s in st)
                                / (len(per) * sum(w.n for w, _ in inst))),
-        "roofline": {
-            "kernel": "k_walk_batch",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-            "stream_copy_gbps": copy_gbps,
-            "stream_add_gbps": add_gbps,
-        },
+        "roofline": walk_roofline("k_walk_batch", "batched96", args.valtype, walk_avg_s,
+                                  sum(wb) / len(wb), ceilings, copy_gbps, add_gbps),
     }
     b.close()
     if not args.no_cpu_baseline:
-        # the oracle's assignment walk on the first objects of successive
-        # instances (their means before the check iteration) until about
-        # --cpu-seconds of CPU work
-        threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-        cm, ct, used, objs = 0, 0.0, 0, 0
-        for i, (w, _) in enumerate(inst):
-            x = data[w.name][0]
-            m = min(w.n, 4000)
-            rows = np.arange(m)
-            t = time.perf_counter()
-            ar = oracle.assign(x.subset(rows), before[i][0], before[i][1][rows], threads=threads)
-            ct += time.perf_counter() - t
-            cm += ar.mult_adds
-            used += 1
-            objs += m
-            if ct >= args.cpu_seconds:
-                break
-        log("cpu baseline: %d objects of %d instances, %.3e mult-adds in %.1fs"
-            % (objs, used, cm, ct))
-        out["cpu_baseline"] = {
-            "value": cm / ct, "unit": "mult-adds/s", "cores": threads, "kind": "oracle",
-            "sample": "FP64 oracle assignment walk of the first %d objects of each of the "
-                      "first %d instances (%d objects) against their current means, %.1fs"
-                      % (4000, used, objs, ct)}
+        out["cpu_baseline"], out["oracle_check"] = batched_cpu_baseline(inst, data, before, after,
+                                                                       args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def batched_cpu_baseline(inst, data, before, after, target_s):
+    """The FP64 oracle on this host's cores over the batched instances' state
+    after the timed iterations: its assignment walk over the first objects of
+    successive instances (from their means and previous assignment) until
+    about target_s of CPU work; the same results check the GPU's next
+    iteration on a seeded sample of 96 objects of every instance."""
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    exact, sampled = 0, 0
+    for i, (w, r) in enumerate(inst):
+        x = data[w.name][0]
+        m = min(w.n, 96)
+        rows = np.sort(datagen.perm_prefix(w.n, m, w.seed + 1000 * r, stream=7))
+        means = oracle.Means(w.k, w.d, *before[i][0])
+        ar = oracle.assign(x.subset(rows), means, before[i][1][rows], threads=threads)
+        exact += int(np.array_equal(after[i][rows], ar.assign))
+        sampled += m
+    log("oracle check: %d of %d instances identical on %d sampled objects"
+        % (exact, len(inst), sampled))
+    cm, ct, used, objs = 0, 0.0, 0, 0
+    for i, (w, _) in enumerate(inst):
+        x = data[w.name][0]
+        m = min(w.n, 4000)
+        rows = np.arange(m)
+        means = oracle.Means(w.k, w.d, *before[i][0])
+        t = time.perf_counter()
+        ar = oracle.assign(x.subset(rows), means, before[i][1][rows], threads=threads)
+        ct += time.perf_counter() - t
+        cm += ar.mult_adds
+        used += 1
+        objs += m
+        if ct >= target_s:
+            break
+    log("cpu baseline: %d objects of %d instances, %.3e mult-adds in %.1fs" % (objs, used, cm, ct))
+    base = {"value": cm / ct, "unit": "mult-adds/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle assignment walk of the first %d objects of each of the "
+                      "first %d instances (%d objects) against their means after the timed "
+                      "iterations, %.1fs" % (4000, used, objs, ct)}
+    return base, {"instances_identical_to_oracle": exact, "instances": len(inst),
+                  "oracle_sampled_objects": sampled}
 
 
 def main():
@@ -594,6 +799,11 @@ def main():
         return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-counters":
         print(json.dumps(summarize_counters(*sys.argv[2:9])))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-levels":
+        a = sys.argv[2:]
+        print(json.dumps(summarize_levels(a[0], a[1], a[2], a[3], a[4], a[5], int(a[6]),
+                                          *a[7:])))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -627,6 +837,12 @@ def main():
         run_ivfd(args)
         return
 
+    run_single(args)
+
+
+def run_single(args):
+    """One workload on one handle: the benchmark's Lloyd chain (default: 8M
+    documents x 140k terms, k = 10,000)."""
     import numpy as np
     import torch
 
@@ -636,6 +852,7 @@ def main():
     if args.calibrate_copy:
         calibration_copies()
     copy_gbps, add_gbps = stream_gbps()
+    ceilings = read_ceilings()
     w = datagen.WORKLOADS[args.workload]
     log("generating %s: n=%d d=%d lambda=%g k=%d" % (w.name, w.n, w.d, w.lam, w.k))
     x = w.generate()
@@ -648,7 +865,8 @@ def main():
                        waves_per_wg=args.waves, objects_per_item=args.chunk)
     km.init_seeds(torch.from_numpy(seeds.astype(np.int32)).to(dev))
     a = torch.full((w.n,), -1, dtype=torch.int32, device=dev)
-    log("built; plan %s" % km.plan)
+    plan = km.plan
+    log("built; plan %s" % plan)
     for r in range(args.warmup):
         sa = km.assign(a)
         su = km.update(a)
@@ -658,10 +876,12 @@ def main():
     torch.cuda.synchronize()
     per = []
     step_ms = []
+    snaps = []
     t_start = time.perf_counter()
     for r in range(args.steps):
         t0 = time.perf_counter()
         sa = km.assign(a)
+        snaps.append(a.clone())   # for the per-iteration hashes, read after the timed region
         su = km.update(a)         # both calls synchronise: the step's wall time
         step_ms.append(1e3 * (time.perf_counter() - t0))
         per.append((sa, su))
@@ -671,17 +891,27 @@ def main():
                                          sa["changed"]))
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
+    hashes = [hashlib.sha256(t.cpu().numpy().tobytes()).hexdigest() for t in snaps]
+    del snaps
 
+    # one more assignment outside the timed region: the state the oracle checks
+    means = km.get_means()
+    check = {"means": tuple(t.cpu().numpy() for t in means), "prev": a.cpu().numpy()}
+    del means
+    sc = km.assign(a)
+    best, best_id, second, _, flags = (t.cpu().numpy() for t in km.get_scores())
+    check.update({"stats": sc, "assign": a.cpu().numpy(), "best": best, "best_id": best_id,
+                  "second": second, "flags": flags})
+
+    R = plan["ranges"]
     mult = sum(p[0]["mult_adds"] for p in per)
     walk_s = sum(p[0]["walk_ms"] for p in per) / 1e3
     assign_s = sum(p[0]["assign_ms"] for p in per) / 1e3
-    bytes_iter = sum(iteration_bytes(p[0]["mult_adds"], x.nnz, x.n, p[1]["nnz_means"],
+    bytes_iter = sum(iteration_bytes(p[0]["mult_adds"], x.nnz, x.n, R, p[1]["nnz_means"],
                                      args.valtype) for p in per)
-    wb = [walk_bytes(p[0]["mult_adds"], x.nnz, x.n, args.valtype) for p in per]
+    wb = [walk_bytes(p[0]["mult_adds"], x.nnz, x.n, R, args.valtype) for p in per]
     walk_avg_s = walk_s / len(per)
-    achieved = (sum(wb) / len(wb)) / walk_avg_s / 1e9
-    traffic = measured_traffic(w.name, args.valtype, None)
-    traffic_gbps = traffic / walk_avg_s / 1e9 if traffic else None
+    algorithmic = (sum(wb) / len(wb)) / walk_avg_s / 1e9
     out = {
         "metric": METRIC,
         "value": args.steps / t_total,
@@ -699,40 +929,29 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "k": w.k, "nnz": x.nnz,
                    "lambda": w.lam, "zipf_s": w.s, "seed": w.seed, "valtype": args.valtype,
-                   "plan": km.plan},
+                   "plan": plan},
         "mult_adds_per_s": mult / t_total,
         "mult_adds_per_s_walk": mult / walk_s,
         "mult_adds_per_iter": mult / len(per),
-        "hbm_gbps_algorithmic": bytes_iter / t_total / 1e9,
+        "gbps_algorithmic_iteration": bytes_iter / t_total / 1e9,
         "assign_ms": 1e3 * assign_s / len(per),
         "walk_ms": 1e3 * walk_avg_s,
         "update_ms": sum(p[1]["update_ms"] for p in per) / len(per),
         "certified_fraction": sum(p[0]["certified"] for p in per) / (len(per) * x.n),
         "rescored_per_iter": sum(p[0]["rescored"] for p in per) / len(per),
-        "max_rel_err": max(p[0]["max_rel_err"] for p in per),
+        "max_rel_err_rescored": max(p[0]["max_rel_err_rescored"] for p in per),
+        "assign_sha256_per_step": hashes,
+        "changed_per_step": [p[0]["changed"] for p in per],
         "objective": per[-1][1]["objective_exact"],
-        "roofline": {
-            "kernel": "k_walk",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-            "traffic_gbps": traffic_gbps,
-            "traffic_frac": traffic_gbps / HBM_PEAK_GBPS if traffic_gbps else None,
-            "stream_copy_gbps": copy_gbps,
-            "stream_add_gbps": add_gbps,
-            "traffic_frac_of_stream": (traffic_gbps / max(copy_gbps, add_gbps)
-                                       if traffic_gbps else None),
-        },
+        "roofline": walk_roofline("k_walk", w.name, args.valtype, walk_avg_s,
+                                  sum(wb) / len(wb), ceilings, copy_gbps, add_gbps),
     }
     km.close()
-    del xd
+    del xd, a
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(x, w.k, w.seed, args.cpu_seconds)
+        out["cpu_baseline"], out["precision_check"] = cpu_baseline(
+            x, w, args.valtype, check, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

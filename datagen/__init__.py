@@ -190,6 +190,9 @@ WORKLOADS = {
     "nyt_like": Workload("nyt_like", 300_000, 100_000, 230.0, 10, 2000, 1.05, 10_000, 20, 2),
     "pubmed_8m": Workload("pubmed_8m", 8_000_000, 140_000, 60.0, 3, 1000, 1.1, 10_000, 10, 3),
     "precision": Workload("precision", 2_000_000, 200_000, 120.0, 5, 1500, 1.1, 50_000, 10, 4),
+    # the paper's 1M-document PubMed sample shape at k = 10,000: its Lloyd chain
+    # still moves hundreds of objects per iteration after 10 iterations
+    "pubmed_1m": Workload("pubmed_1m", 1_000_000, 140_000, 60.0, 3, 1000, 1.1, 10_000, 10, 9),
 }
 
 

@@ -112,7 +112,9 @@ typedef struct {
     int64_t rescored;        /* objects re-scored in FP64 */
     int64_t zero_overlap;    /* objects sharing no term with any mean */
     int64_t mult_adds;       /* M = sum_i sum_h (nc)_{t(i,h)} (the paper's Eq. ivf_mult) */
-    double max_rel_err;      /* max |rho~ - rho64| / rho64 over re-scored objects' winners */
+    double max_rel_err_rescored; /* max |rho~ - rho64| / rho64 of the FP32 winner, over the
+                                objects re-scored in FP64 (certified objects are not
+                                scored in FP64, so they do not enter it) */
     float assign_ms;         /* device time of the assignment step */
     float walk_ms;           /* device time of its inverted-file walk kernel alone */
     /* update step */
@@ -127,6 +129,14 @@ typedef struct {
 /*
  * ivf_build: validate the object set, derive its term-major view and plan the
  * launch shapes.  No means exist yet: call ivf_set_means or ivf_init_seeds.
+ * This is the problem statement of the paper's Section "Lloyd-Type k-Means
+ * Clustering Algorithm" (an object set X of N points in D dimensions and a
+ * positive integer k); the initial state is given separately, as the method
+ * starts from a given initial state (Section "Proposed algorithm: IVF": IVF
+ * keeps the standard Lloyd solution under an identical initial state).  The
+ * caller gives k here and the initial means later (ivf_set_means, or
+ * ivf_init_seeds for k seed objects), so one validated object set can be
+ * clustered from several initial states.
  *   X     object set (device pointers, borrowed, see ivf_csr)
  *   k     number of clusters, 1 <= k <= n, k < 2^24
  *   opts  NULL for defaults
@@ -169,15 +179,22 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats);
 ivf_status ivf_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats);
 
 /*
- * ivf_iterate: `iters` Lloyd iterations (assignment then update).  assign as
- * in ivf_assign.  per_iter (host, [iters]) may be NULL.
+ * ivf_iterate: `iters` Lloyd iterations (assignment then update), the
+ * two-step repetition of the paper's Section "Lloyd-Type k-Means Clustering
+ * Algorithm" run to a predetermined termination condition (a fixed count);
+ * each iteration is Algorithm 3 at iteration r.  assign as in ivf_assign.
+ * per_iter (host, [iters]) may be NULL; it receives each iteration's
+ * assignment and update fields.  Synchronises (as ivf_update does).
  */
 ivf_status ivf_iterate(ivf_handle* h, int32_t iters, int32_t* assign, ivf_stats* per_iter);
 
 /*
  * ivf_converge: Lloyd iterations until an assignment step changes no object's
  * cluster (the partition, and hence the means, are then a fixed point of the
- * iteration), or max_iters assignment steps.  The converged step's update is
+ * iteration), or max_iters assignment steps.  This is the "until the
+ * convergence" of the paper's Section "Lloyd-Type k-Means Clustering
+ * Algorithm", which leaves convergence undefined; here it means no change of
+ * cluster.  The converged step's update is
  * skipped: it would return the same means.  assign as in ivf_assign;
  * per_iter (host, [max_iters]) may be NULL; *iters_done receives the number
  * of assignment steps run (the last has changed == 0 unless max_iters was
@@ -215,8 +232,11 @@ ivf_status ivf_assign_ivfd(ivf_handle* h, int32_t objects_per_range, int32_t* as
                            ivf_stats* stats);
 
 /*
- * ivf_get_means: two-call copy of the current means.  With out->indptr NULL
- * only out->k, out->d and out->nnz are filled; otherwise the caller's device
+ * ivf_get_means: two-call copy of the current means: the content of the
+ * inverted mean file M-breve that Algorithm 3 returns (Section "Proposed
+ * algorithm: IVF"), given mean-major in FP64 (per cluster j its ascending
+ * (term p, u_p = w_p / ||w||) entries) rather than term-major.  With
+ * out->indptr NULL only out->k, out->d and out->nnz are filled; otherwise the caller's device
  * buffers (indptr[k+1], indices[nnz], values[nnz], nnz from the first call)
  * receive the mean-major FP64 means.  Synchronises.
  */
@@ -251,13 +271,24 @@ ivf_status ivf_plan_shape(int32_t k, const ivf_options* opts, int32_t plan[7]);
 
 /*
  * ivf_cert_bound: the certification constants for an object of `nt`
- * nonzeros and the given value type (host only): c[0] relative bound of an
- * FP32 tile score against the exact score, c[1] absolute term, c[2] relative
- * bound of the FP64 reference's own rounding.  The test certifying cluster a
- * over every other cluster b is
+ * nonzeros, the given value type and objects whose values are all <= vmax
+ * (host only).  The bound is the recursive-summation error bound of a sum of
+ * non-negative products (the FP64 reference's own rounding is c[2]).
+ *   c[0] relative bound of an FP32 tile score against the exact score:
+ *        ((1 + u_s)(1 + gamma_nt) - 1) * 1.01 + 1e-15, with u_s the unit
+ *        roundoff of the stored mean value (FP32 2^-24; BF16 and FP16 their
+ *        own plus the FP32 step) and gamma_nt = nt 2^-24 / (1 - nt 2^-24);
+ *   c[1] absolute term for results below the normal range:
+ *        nt (vmax eta_m + 2 eta) (1 + gamma_nt) * 1.01, eta = 2^-126 (one FP32
+ *        rounding of a tiny result, kept subnormal or flushed), eta_m = eta for
+ *        FP32 and BF16 values, 2^-25 + eta for FP16 values (FP16 subnormals);
+ *   c[2] relative bound of the FP64 reference's rounding (gamma_nt in FP64).
+ * The test certifying cluster a over every other cluster b is
  *   (s_a - c[1]) (1 - c[2]) / (1 + c[0])  >  (s_b + c[1]) (1 + c[2]) / (1 - c[0]).
+ * The library uses vmax = the largest value of the handle's object set.
+ * IVF_ERR_ARG for an unknown valtype, nt < 0 or vmax not finite and >= 0.
  */
-ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]);
+ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double vmax, double c[3]);
 
 /*
  * ivf_cert_bound_fixed: the same constants for the fixed-point scores of
@@ -265,10 +296,28 @@ ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]);
  * value and the object value, times `scale` (a power of two), rounded to the
  * nearest integer; the integers summed exactly; the sum converted to FP32 and
  * divided by scale.  c[0] = ((1 + 2^-24)^3 - 1) * 1.01 + 1e-15, c[1] =
- * nt * (1/(2 scale) + 2^-149) * (1 + 2^-24) * 1.01, c[2] as above.
- * IVF_ERR_ARG for nt < 0 or a scale that is not a positive finite number.
+ * nt * (1/(2 scale) + (vmax + 1) 2^-126) * (1 + 2^-24) * 1.01, c[2] as above.
+ * IVF_ERR_ARG for nt < 0, a scale that is not a positive finite number, or
+ * vmax not finite and >= 0.
  */
-ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double c[3]);
+ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double vmax, double c[3]);
+
+/*
+ * ivf_read_ceiling: a measurement utility, not a step of the method: the
+ * read bandwidth of a plain 16-byte-per-lane streaming read kernel over the
+ * caller's device buffer `buf` of `bytes` bytes (>= 16 KiB; its contents are
+ * irrelevant), the roof against which the assignment walk's cache and memory
+ * traffic is placed.  mode 0: every workgroup reads the whole buffer (a few
+ * MB stay resident in each L2); mode 1: the workgroups split the buffer and
+ * sweep it `passes` times (a buffer between the L2s' and the Infinity
+ * Cache's sizes is served by the latter, GBs by HBM).  One untimed launch
+ * warms the caches, one launch is timed with HIP events on `stream`
+ * (hipStream_t, NULL = null stream); *gbps receives bytes read / time in
+ * GB/s.  Allocates and frees a small sink buffer; synchronises the stream.
+ * IVF_ERR_ARG for bad arguments, IVF_ERR_HIP / IVF_ERR_OOM on HIP failures.
+ */
+ivf_status ivf_read_ceiling(const void* buf, int64_t bytes, int32_t mode, int32_t passes,
+                            void* stream, double* gbps);
 
 /* Frees the handle and everything it owns (NULL is a no-op). */
 void ivf_destroy(ivf_handle* h);

@@ -20,7 +20,8 @@ def library():
 
 VALTYPES = {"f32": IVF_VAL_F32, "bf16": IVF_VAL_BF16, "f16": IVF_VAL_F16}
 
-__all__ = ["IVFKMeans", "IVFBatch", "IvfError", "VALTYPES", "plan_shape", "cert_bound"]
+__all__ = ["IVFKMeans", "IVFBatch", "IvfError", "VALTYPES", "plan_shape", "cert_bound",
+           "cert_bound_fixed", "read_ceiling"]
 
 
 def _ptr(t):
@@ -60,20 +61,38 @@ def plan_shape(k, **opts):
     return dict(zip(keys, list(plan)))
 
 
-def cert_bound(valtype, nt):
-    """(c, a, g64) certification constants for an object of nt nonzeros."""
+def cert_bound(valtype, nt, vmax=1.0):
+    """(c, a, g64) certification constants for an object of nt nonzeros, all
+    object values <= vmax."""
     c = (ctypes.c_double * 3)()
     vt = VALTYPES[valtype] if isinstance(valtype, str) else int(valtype)
-    check(_lib.get().ivf_cert_bound(vt, int(nt), c))
+    check(_lib.get().ivf_cert_bound(vt, int(nt), float(vmax), c))
     return tuple(c)
 
 
-def cert_bound_fixed(nt, scale):
+def cert_bound_fixed(nt, scale, vmax=1.0):
     """(c, a, g64) constants of IVFD's fixed-point scores (products scaled by
-    `scale` and rounded to integers) for an object of nt nonzeros."""
+    `scale` and rounded to integers) for an object of nt nonzeros, all object
+    values <= vmax."""
     c = (ctypes.c_double * 3)()
-    check(_lib.get().ivf_cert_bound_fixed(int(nt), float(scale), c))
+    check(_lib.get().ivf_cert_bound_fixed(int(nt), float(scale), float(vmax), c))
     return tuple(c)
+
+
+def read_ceiling(buf, mode, passes, stream=None):
+    """Read bandwidth (GB/s) of a plain streaming read of the CUDA tensor `buf`
+    (mode 0: every workgroup reads all of it; mode 1: split and swept
+    `passes` times): the measured roofs of the walk's traffic."""
+    import torch
+    if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
+        raise TypeError("buf must be a contiguous CUDA tensor")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    out = ctypes.c_double()
+    check(_lib.get().ivf_read_ceiling(_ptr(buf), buf.numel() * buf.element_size(), int(mode),
+                                      int(passes), ctypes.c_void_p(stream) if stream else None,
+                                      ctypes.byref(out)))
+    return out.value
 
 
 class IVFKMeans:

@@ -41,8 +41,8 @@ class ivf_options(ctypes.Structure):
 class ivf_stats(ctypes.Structure):
     _fields_ = [("objective", c_double), ("objective_bound", c_double), ("changed", c_int64),
                 ("certified", c_int64), ("rescored", c_int64), ("zero_overlap", c_int64),
-                ("mult_adds", c_int64), ("max_rel_err", c_double), ("assign_ms", c_float),
-                ("walk_ms", c_float),
+                ("mult_adds", c_int64), ("max_rel_err_rescored", c_double),
+                ("assign_ms", c_float), ("walk_ms", c_float),
                 ("objective_exact", c_double), ("empty_clusters", c_int64),
                 ("nnz_means", c_int64), ("inexact_terms", c_int64), ("update_ms", c_float)]
 
@@ -67,8 +67,11 @@ SIGNATURES = {
     "ivf_get_scores": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ivf_get_plan": (c_int32, [c_void_p, ctypes.POINTER(c_int32)]),
     "ivf_plan_shape": (c_int32, [c_int32, ctypes.POINTER(ivf_options), ctypes.POINTER(c_int32)]),
-    "ivf_cert_bound": (c_int32, [c_int32, c_int64, ctypes.POINTER(c_double)]),
-    "ivf_cert_bound_fixed": (c_int32, [c_int64, c_double, ctypes.POINTER(c_double)]),
+    "ivf_cert_bound": (c_int32, [c_int32, c_int64, c_double, ctypes.POINTER(c_double)]),
+    "ivf_cert_bound_fixed": (c_int32, [c_int64, c_double, c_double,
+                                       ctypes.POINTER(c_double)]),
+    "ivf_read_ceiling": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p,
+                                   ctypes.POINTER(c_double)]),
     "ivf_destroy": (None, [c_void_p]),
     "ivf_last_error": (ctypes.c_char_p, [c_void_p]),
     "ivf_status_str": (ctypes.c_char_p, [c_int32]),

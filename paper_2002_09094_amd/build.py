@@ -24,6 +24,9 @@ FLAGS = [
     # IEEE order of operations: no FMA contraction (the FP64 re-score must
     # reproduce the reference's separate multiply and add)
     "-ffp-contract=off",
+    # subnormal FP32, FP16 and FP64 results are kept, not flushed (the
+    # certification bound's absolute term for FP16 mean values relies on it)
+    "-fno-gpu-flush-denormals-to-zero",
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -117,6 +117,8 @@ struct ObjView {
     uint32_t* optr = nullptr;   // [o_R * d + 1]
     uint2* opost = nullptr;     // [nnz]
     double o_maxnorm = 0.0;     // largest object L2 norm
+    double vmax = 0.0;          // largest object value
+    int64_t nmax = 0;           // longest object row
 
     void release() { dfree(xt_obj); dfree(xt_tv); dfree(shift); dfree(optr); dfree(opost); }
 };
@@ -141,6 +143,7 @@ struct ivf_handle {
     int cur = 0;
     bool has_means = false;
     bool nnzM_known = true;    // false while the count lives only on the device
+    double mmax = 1.0;         // largest mean value any current mean may hold
     int64_t nnzM = 0;
     int64_t mm_cap[2] = {0, 0};
     int64_t* mm_ptr[2] = {nullptr, nullptr};
@@ -292,10 +295,11 @@ ivf_status ensure_slab(ivf_handle* h, int64_t elems) {
     return IVF_OK;
 }
 
-ivf_status read_errors(ivf_handle* h, const char* what) {
+ivf_status read_errors(ivf_handle* h, const char* what, Counters* out = nullptr) {
     Counters c;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
+    if (out) *out = c;
     const unsigned long long f = c.error_flags;
     if (!f) return IVF_OK;
     std::string m = std::string(what) + ": ";
@@ -305,6 +309,20 @@ ivf_status read_errors(ivf_handle* h, const char* what) {
     if (f & kBadOrder) return fail(h, IVF_ERR_UNSORTED, m + "term ids not strictly ascending");
     if (f & kNonFinite) return fail(h, IVF_ERR_NONFINITE, m + "non-finite value");
     return fail(h, IVF_ERR_NEGATIVE, m + "value <= 0");
+}
+
+// FP32 scores must stay finite: every score is at most (longest row) x
+// (largest object value) x (largest mean value), kept below 2^120; FP16 mean
+// values must fit FP16's range.
+ivf_status check_value_range(ivf_handle* h, double mmax) {
+    const double top = (double)std::max<int64_t>(h->ov->nmax, 1) * h->ov->vmax * mmax;
+    if (!(top < 0x1p120) || !(mmax < 0x1p120))
+        return fail(h, IVF_ERR_CAPACITY,
+                    "values too large: FP32 scores could overflow (rows x largest object value "
+                    "x largest mean value >= 2^120)");
+    if (h->opt.valtype == IVF_VAL_F16 && mmax >= 65504.0)
+        return fail(h, IVF_ERR_CAPACITY, "a mean value is beyond FP16's range (>= 65504)");
+    return IVF_OK;
 }
 
 // Default share of a range's clusters from which a (term, range) slice is a
@@ -450,6 +468,7 @@ ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0,
     m.x_ptr = h->ov->x_ptr; m.n = h->n; m.R = R > 0 ? R : p.R;
     m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
     m.fixed_scale = fixed_scale;
+    m.vmax = h->ov->vmax;
     m.rec = rec ? rec : h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
     m.best = h->best; m.best_id = h->best_id; m.second = h->second; m.flags = h->flags;
     m.rescore_list = h->rescore_list; m.cnt = h->cnt;
@@ -460,6 +479,7 @@ ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0,
         r.mm_ptr = h->mm_ptr[h->cur]; r.mm_idx = h->mm_idx[h->cur]; r.mm_val = h->mm_val[h->cur];
         r.valtype = h->opt.valtype;
         r.fixed_scale = fixed_scale;
+        r.vmax = h->ov->vmax;
         r.rec = rec ? nullptr : h->rec;   // another walk's records bound other ranges
         r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
         r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
@@ -490,7 +510,7 @@ ivf_status assign_stats(ivf_handle* h, ivf_stats* stats, bool timed) {
     stats->rescored = (int64_t)c.n_rescore;
     stats->zero_overlap = (int64_t)c.zero_overlap;
     stats->mult_adds = (int64_t)c.mult;
-    stats->max_rel_err = err;
+    stats->max_rel_err_rescored = err;
     stats->assign_ms = ms;
     stats->walk_ms = wms;
     stats->objective_exact = std::nan("");
@@ -566,8 +586,11 @@ ivf_status build_objview(ivf_handle* h, const ivf_csr* X) {
     HIPCHK(h, launch_clear_counters(h->cnt, h->stream));
     ObjectView xv{X->indptr, X->indices, X->values, n, d, nnz};
     HIPCHK(h, launch_validate_objects(xv, h->cnt, h->stream));
-    ivf_status st = read_errors(h, "objects");
+    Counters vc;
+    ivf_status st = read_errors(h, "objects", &vc);
     if (st != IVF_OK) return st;
+    std::memcpy(&ov->vmax, &vc.vmax_bits, sizeof(double));
+    ov->nmax = (int64_t)vc.nmax;
     st = ensure_scratch(h, std::max<int64_t>(nnz, 1));
     if (st != IVF_OK) return st;
     Scratch* sc = h->sc;
@@ -596,7 +619,7 @@ ivf_status build_objview(ivf_handle* h, const ivf_csr* X) {
     Counters c;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     HIPCHK(h, hipMemcpy(&c, h->cnt, sizeof(c), hipMemcpyDeviceToHost));
-    ov->inexact = (int64_t)c.pad[0];
+    ov->inexact = (int64_t)c.inexact;
     (void)hipFree(rowid);
     (void)hipFree(emin);
     (void)hipFree(emax);
@@ -710,6 +733,8 @@ ivf_status create_handle(const ivf_csr* X, int32_t k, const ivf_options& o, Scra
     ivf_status st = IVF_OK;
     if (!ov) st = build_objview(h, X);
     else st = ensure_scratch(h, std::max<int64_t>(X->nnz, 1));
+    // means of the update are unit-norm: the objects alone must keep scores finite
+    if (st == IVF_OK) st = check_value_range(h, 1.0);
     if (st == IVF_OK) st = alloc_handle(h);
     if (st == IVF_OK) {
         e = hipStreamSynchronize(h->stream);
@@ -1118,15 +1143,19 @@ ivf_status ivf_get_plan(const ivf_handle* h, int32_t plan[7]) {
     return IVF_OK;
 }
 
-ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double c[3]) {
-    if (!c || valtype < IVF_VAL_F32 || valtype > IVF_VAL_F16 || nt < 0) return IVF_ERR_ARG;
-    cert_consts(valtype, nt, &c[0], &c[1], &c[2]);
+ivf_status ivf_cert_bound(int32_t valtype, int64_t nt, double vmax, double c[3]) {
+    if (!c || valtype < IVF_VAL_F32 || valtype > IVF_VAL_F16 || nt < 0 || !(vmax >= 0.0) ||
+        !std::isfinite(vmax))
+        return IVF_ERR_ARG;
+    cert_consts(valtype, nt, vmax, &c[0], &c[1], &c[2]);
     return IVF_OK;
 }
 
-ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double c[3]) {
-    if (!c || nt < 0 || !(scale > 0.0) || !std::isfinite(scale)) return IVF_ERR_ARG;
-    cert_consts_fixed(nt, scale, &c[0], &c[1], &c[2]);
+ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double vmax, double c[3]) {
+    if (!c || nt < 0 || !(scale > 0.0) || !std::isfinite(scale) || !(vmax >= 0.0) ||
+        !std::isfinite(vmax))
+        return IVF_ERR_ARG;
+    cert_consts_fixed(nt, scale, vmax, &c[0], &c[1], &c[2]);
     return IVF_OK;
 }
 
@@ -1162,7 +1191,14 @@ ivf_status ivf_set_means(ivf_handle* h, const ivf_means* M) {
     HIPCHK(h, launch_clear_counters(h->cnt, h->stream));
     HIPCHK(h, launch_validate_means(M->indptr, M->indices, M->values, h->k, h->d, M->nnz, h->cnt,
                                     h->stream));
-    ivf_status st = read_errors(h, "means");
+    Counters vc;
+    ivf_status st = read_errors(h, "means", &vc);
+    if (st != IVF_OK) return st;
+    double mmax = 0.0;
+    std::memcpy(&mmax, &vc.vmax_bits, sizeof(double));
+    // rows the update keeps (empty clusters) may hold earlier means' values
+    mmax = std::max(mmax, 1.0);
+    st = check_value_range(h, mmax);
     if (st != IVF_OK) return st;
     const int b = h->cur;
     st = ensure_mm(h, b, M->nnz);
@@ -1181,6 +1217,7 @@ ivf_status ivf_set_means(ivf_handle* h, const ivf_means* M) {
     h->nnzM = M->nnz;
     h->nnzM_known = true;
     h->has_means = true;
+    h->mmax = mmax;
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return IVF_OK;
 }

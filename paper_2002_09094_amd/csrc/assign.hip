@@ -483,10 +483,13 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
         } else {
             double c, ab, g;
             if (a.fixed_scale > 0.0)
-                cert_consts_fixed(a.x_ptr[i + 1] - a.x_ptr[i], a.fixed_scale, &c, &ab, &g);
+                cert_consts_fixed(a.x_ptr[i + 1] - a.x_ptr[i], a.fixed_scale, a.vmax, &c, &ab,
+                                  &g);
             else
-                cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], &c, &ab, &g);
-            const bool ok = !a.force_rescore && b > 0.f &&
+                cert_consts(a.valtype, a.x_ptr[i + 1] - a.x_ptr[i], a.vmax, &c, &ab, &g);
+            // a non-finite score certifies nothing (the library rejects inputs
+            // whose FP32 scores could overflow; this keeps the rule total)
+            const bool ok = !a.force_rescore && b > 0.f && isfinite(b) && isfinite(s2) &&
                             cert_lb((double)b, c, ab, g) > cert_ub((double)s2, c, ab, g);
             if (ok || !a.certify) {
                 a.assign[i] = id >= 0 ? id : prev;
@@ -578,13 +581,13 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
         const int32_t prev = a.prev[i];
         const int32_t fw = a.best_id[i];
         double c, ab, g;
-        cert_consts(a.valtype, he - hb, &c, &ab, &g);
+        cert_consts(a.valtype, he - hb, a.vmax, &c, &ab, &g);
         // the winner's score may come from another walk (IVFD's fixed-point
         // sums): its lower bound then uses that walk's constants
         double thr;
         if (a.fixed_scale > 0.0) {
             double c1, ab1, g1;
-            cert_consts_fixed(he - hb, a.fixed_scale, &c1, &ab1, &g1);
+            cert_consts_fixed(he - hb, a.fixed_scale, a.vmax, &c1, &ab1, &g1);
             thr = cert_lb((double)a.best[i], c1, ab1, g1);
         } else {
             thr = cert_lb((double)a.best[i], c, ab, g);

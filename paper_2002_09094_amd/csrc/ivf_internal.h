@@ -59,7 +59,9 @@ struct Counters {
     unsigned long long error_flags;    // validation
     unsigned long long walked;         // entries the IVFD walk met
     unsigned long long norm_bits;      // largest row norm (double bits, >= 0)
-    unsigned long long pad[3];
+    unsigned long long inexact;        // terms whose fixed-point member sums are rounded
+    unsigned long long vmax_bits;      // validation: largest value (double bits, >= 0)
+    unsigned long long nmax;           // validation: longest row
 };
 
 // Error flags raised by the validation kernels.
@@ -80,21 +82,39 @@ __device__ inline int64_t bounded_count(int64_t n, const int64_t* n_dev) {
     return (v >= 0 && v <= n) ? v : 0;
 }
 
-// Certification constants: see ivf_cert_bound in ivf.h.
-__host__ __device__ inline void cert_consts(int valtype, int64_t nt, double* c, double* a,
-                                            double* g64) {
+// Absolute rounding terms of the certificate.  kEtaF32: the largest error of
+// one FP32 (or BF16) rounding of a result below the normal range, whether it
+// is kept as a subnormal (at most 2^-150) or flushed to zero (below 2^-126);
+// 2^-126 covers both.  kEtaF16: half the smallest FP16 subnormal, the error of
+// rounding a mean value below FP16's normal range (the library is built with
+// FP16 denormals kept).
+constexpr double kEtaF32 = 0x1p-126;
+constexpr double kEtaF16 = 0x1p-25;
+
+// Certification constants: see ivf_cert_bound in ivf.h.  vmax bounds every
+// object value.  Per product of the walk: the stored mean value differs from
+// the FP64 one by at most u_s relatively plus eta_m absolutely (below the
+// stored type's normal range), scaled by the object value (<= vmax); the
+// product's and the sum's roundings add u relatively and eta absolutely each.
+__host__ __device__ inline void cert_consts(int valtype, int64_t nt, double vmax, double* c,
+                                            double* a, double* g64) {
     const double u32 = 0x1p-24, u64 = 0x1p-53;
-    double us;
-    if (valtype == IVF_VAL_F32) us = u32;
-    else if (valtype == IVF_VAL_BF16) us = 0x1p-8 + u32 + 0x1p-32;   // FP64 -> FP32 -> BF16
-    else us = 0x1p-11 + u32 + 0x1p-35;                               // FP64 -> FP32 -> FP16
+    double us, eta_m;
+    if (valtype == IVF_VAL_F32) {
+        us = u32;
+        eta_m = kEtaF32;
+    } else if (valtype == IVF_VAL_BF16) {
+        us = 0x1p-8 + u32 + 0x1p-32;   // FP64 -> FP32 -> BF16
+        eta_m = kEtaF32;
+    } else {
+        us = 0x1p-11 + u32 + 0x1p-35;  // FP64 -> FP32 -> FP16
+        eta_m = kEtaF16 + kEtaF32;
+    }
     const double n = (double)(nt > 0 ? nt : 1);
     const double g32 = n * u32 / (1.0 - n * u32);
     double cc = (1.0 + us) * (1.0 + g32) - 1.0;
     *c = cc * 1.01 + 1e-15;
-    // FP16 subnormal / flushed mean values: |m~ - m| <= 2^-25 absolutely; the
-    // object's values are <= 1, so the score moves by at most nt * 2^-25.
-    *a = (valtype == IVF_VAL_F16) ? n * 0x1p-25 * (1.0 + g32) * 1.01 : 0.0;
+    *a = n * (vmax * eta_m + 2.0 * kEtaF32) * (1.0 + g32) * 1.01;
     *g64 = (n * u64 / (1.0 - n * u64)) * 1.01 + 1e-17;
 }
 
@@ -103,15 +123,16 @@ __host__ __device__ inline void cert_consts(int valtype, int64_t nt, double* c, 
 // by `scale` (a power of two) and rounded to the nearest integer; the nt
 // integers summed exactly; the sum converted to FP32 and divided by scale.
 // Relative: the two FP32 roundings before the sum and the one after; absolute:
-// half a unit of 1 / scale per product (plus the FP32 underflow spacing of a
-// product, 2^-149 each).  g64 as for cert_consts.
-__host__ __device__ inline void cert_consts_fixed(int64_t nt, double scale, double* c, double* a,
-                                                  double* g64) {
+// half a unit of 1 / scale per product, plus the FP32 roundings of the mean
+// value (times the object value, <= vmax) and of the product below the normal
+// range.  g64 as for cert_consts.
+__host__ __device__ inline void cert_consts_fixed(int64_t nt, double scale, double vmax,
+                                                  double* c, double* a, double* g64) {
     const double u32 = 0x1p-24, u64 = 0x1p-53;
     const double n = (double)(nt > 0 ? nt : 1);
     const double cc = (1.0 + u32) * (1.0 + u32) * (1.0 + u32) - 1.0;
     *c = cc * 1.01 + 1e-15;
-    *a = n * (0.5 / scale + 0x1p-149) * (1.0 + u32) * 1.01;
+    *a = n * (0.5 / scale + (vmax + 1.0) * kEtaF32) * (1.0 + u32) * 1.01;
     *g64 = (n * u64 / (1.0 - n * u64)) * 1.01 + 1e-17;
 }
 

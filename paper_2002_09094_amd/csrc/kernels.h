@@ -25,6 +25,7 @@ struct MergeArgs {
     int32_t R;
     int32_t valtype, certify, force_rescore;
     double fixed_scale;       // > 0: the records hold fixed-point sums (IVFD) of this scale
+    double vmax;              // largest object value (the certificate's absolute terms)
     const RangeRec* rec;
     const int32_t* prev;
     int32_t* assign;
@@ -44,6 +45,7 @@ struct RescoreArgs {
     const double* mm_val;
     int32_t valtype;
     double fixed_scale;       // > 0: `best` is a fixed-point sum (IVFD) of this scale
+    double vmax;              // largest object value (the certificate's absolute terms)
     const RangeRec* rec;      // the walk's range records, [n * w.R] (null: re-walk every range)
     const int32_t* rescore_list;
     const int32_t* prev;

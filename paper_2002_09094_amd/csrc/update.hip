@@ -29,28 +29,52 @@ inline unsigned grid_for(int64_t n, int per_thread = 1) {
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Largest value (as double bits: non-negative doubles order like their bit
+// patterns) and longest row of a wave's rows, one atomic each per wave.
+__device__ inline void wave_max_out(double vmax, int64_t len, Counters* cnt) {
+    unsigned long long vb = (unsigned long long)__double_as_longlong(vmax);
+    unsigned long long lb = (unsigned long long)len;
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+        const unsigned long long ov = (unsigned long long)__shfl_xor((long long)vb, o, kWave);
+        const unsigned long long ol = (unsigned long long)__shfl_xor((long long)lb, o, kWave);
+        vb = ov > vb ? ov : vb;
+        lb = ol > lb ? ol : lb;
+    }
+    if (lane_id() == 0) {
+        if (vb) atomicMax(&cnt->vmax_bits, vb);
+        if (lb) atomicMax(&cnt->nmax, lb);
+    }
+}
+
 __global__ void k_validate_objects(ObjectView x, Counters* cnt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && (x.x_ptr[0] != 0 || x.x_ptr[x.n] != x.nnz))
         atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
-    if (i >= x.n) return;
-    const int64_t a = x.x_ptr[i], b = x.x_ptr[i + 1];
-    if (a < 0 || b < a || b > x.nnz) {
-        atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
-        return;
-    }
     unsigned f = 0;
-    int32_t prevt = -1;
-    for (int64_t e = a; e < b; ++e) {
-        const int32_t t = x.x_idx[e];
-        const float v = x.x_val[e];
-        if (t < 0 || t >= x.d) f |= kBadIndex;
-        else if (t <= prevt) f |= kBadOrder;
-        prevt = t;
-        if (!isfinite(v)) f |= kNonFinite;
-        else if (!(v > 0.f)) f |= kNonPositive;
+    double vmax = 0.0;
+    int64_t len = 0;
+    if (i < x.n) {
+        const int64_t a = x.x_ptr[i], b = x.x_ptr[i + 1];
+        if (a < 0 || b < a || b > x.nnz) {
+            f = kBadPtr;
+        } else {
+            len = b - a;
+            int32_t prevt = -1;
+            for (int64_t e = a; e < b; ++e) {
+                const int32_t t = x.x_idx[e];
+                const float v = x.x_val[e];
+                if (t < 0 || t >= x.d) f |= kBadIndex;
+                else if (t <= prevt) f |= kBadOrder;
+                prevt = t;
+                if (!isfinite(v)) f |= kNonFinite;
+                else if (!(v > 0.f)) f |= kNonPositive;
+                else vmax = fmax(vmax, (double)v);
+            }
+        }
     }
     if (f) atomicOr(&cnt->error_flags, (unsigned long long)f);
+    wave_max_out(vmax, len, cnt);
 }
 
 __global__ void k_validate_means(const int64_t* ptr, const int32_t* idx, const double* val,
@@ -58,24 +82,30 @@ __global__ void k_validate_means(const int64_t* ptr, const int32_t* idx, const d
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j == 0 && (ptr[0] != 0 || ptr[k] != nnz))
         atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
-    if (j >= k) return;
-    const int64_t a = ptr[j], b = ptr[j + 1];
-    if (a < 0 || b < a || b > nnz) {
-        atomicOr(&cnt->error_flags, (unsigned long long)kBadPtr);
-        return;
-    }
     unsigned f = 0;
-    int32_t prevt = -1;
-    for (int64_t e = a; e < b; ++e) {
-        const int32_t t = idx[e];
-        const double v = val[e];
-        if (t < 0 || t >= d) f |= kBadIndex;
-        else if (t <= prevt) f |= kBadOrder;
-        prevt = t;
-        if (!isfinite(v)) f |= kNonFinite;
-        else if (!(v > 0.0)) f |= kNonPositive;
+    double vmax = 0.0;
+    int64_t len = 0;
+    if (j < k) {
+        const int64_t a = ptr[j], b = ptr[j + 1];
+        if (a < 0 || b < a || b > nnz) {
+            f = kBadPtr;
+        } else {
+            len = b - a;
+            int32_t prevt = -1;
+            for (int64_t e = a; e < b; ++e) {
+                const int32_t t = idx[e];
+                const double v = val[e];
+                if (t < 0 || t >= d) f |= kBadIndex;
+                else if (t <= prevt) f |= kBadOrder;
+                prevt = t;
+                if (!isfinite(v)) f |= kNonFinite;
+                else if (!(v > 0.0)) f |= kNonPositive;
+                else vmax = fmax(vmax, v);
+            }
+        }
     }
     if (f) atomicOr(&cnt->error_flags, (unsigned long long)f);
+    wave_max_out(vmax, len, cnt);
 }
 
 __global__ void k_row_ids(const int64_t* ptr, int64_t n, int32_t* rowid) {
@@ -146,7 +176,7 @@ __global__ void k_term_shift(const int32_t* emin, const int32_t* emax, const int
     int32_t s = s_exact;
     if (need > 62) {
         s += need - 62;
-        atomicAdd(&cnt->pad[0], 1ull);   // terms whose sums are rounded
+        atomicAdd(&cnt->inexact, 1ull);   // terms whose sums are rounded
     }
     shift[t] = (int16_t)s;
 }

@@ -87,13 +87,19 @@ def _exact_gamma(n, u):
                                    ("f16", Fraction(1, 2 ** 11) + Fraction(1, 2 ** 24) +
                                     Fraction(1, 2 ** 35))])
 @pytest.mark.parametrize("nt", [1, 60, 2000])
-def test_cert_constants_follow_recursive_summation_bound(vt, us, nt):
-    c, a, g = ivf.cert_bound(vt, nt)
+@pytest.mark.parametrize("vmax", [0.5, 1.0, 50.0])
+def test_cert_constants_follow_recursive_summation_bound(vt, us, nt, vmax):
+    c, a, g = ivf.cert_bound(vt, nt, vmax)
     u32 = Fraction(1, 2 ** 24)
     want = (1 + us) * (1 + _exact_gamma(nt, u32)) - 1
     assert c >= float(want) * 1.01 and c <= float(want) * 1.0101 + 1e-14
     assert g >= float(_exact_gamma(nt, Fraction(1, 2 ** 53)))
-    assert (a > 0) == (vt == "f16")
+    # absolute term: per product, the mean value's rounding below the normal
+    # range (times the object value) and two FP32 roundings of tiny results
+    eta = Fraction(1, 2 ** 126)
+    eta_m = eta + (Fraction(1, 2 ** 25) if vt == "f16" else 0)
+    a_want = nt * (Fraction(vmax) * eta_m + 2 * eta) * (1 + _exact_gamma(nt, u32))
+    assert a >= float(a_want) * 1.01 * (1 - 1e-12) and a <= float(a_want) * 1.0101
 
 
 def _round_bf16(x32):
@@ -155,9 +161,60 @@ def test_cert_bound_holds_for_emulated_fp32_scores(vt, fused):
             else:
                 acc = np.float32(acc + np.float32(v[t] * us[t]))
         exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
-        c, a, _ = ivf.cert_bound(vt, nt)
+        c, a, _ = ivf.cert_bound(vt, nt, float(v.max()))
         err = abs(Fraction(float(acc)) - exact)
         assert err <= Fraction(c) * exact + Fraction(a), (vt, trial, float(err), float(exact))
+
+
+def _stored(vt, u):
+    u32 = u.astype(np.float32)
+    if vt == "bf16":
+        return _round_bf16(u32)
+    if vt == "f16":
+        return u32.astype(np.float16).astype(np.float32)
+    return u32
+
+
+def _emulate(vt, v, u, fused):
+    us = _stored(vt, u)
+    acc = np.float32(0)
+    for t in range(len(v)):
+        if fused:
+            acc = _round_f32(Fraction(float(acc)) + Fraction(float(v[t])) * Fraction(float(us[t])))
+        else:
+            acc = np.float32(acc + np.float32(v[t] * us[t]))
+    return acc
+
+
+@pytest.mark.parametrize("vt,fused", [("f32", False), ("bf16", True), ("f16", True)])
+def test_cert_bound_holds_below_the_normal_range(vt, fused):
+    """Adversarial magnitudes below FP32's (or FP16's) normal range: mean
+    values that round to subnormals, products that underflow, and object
+    values far above 1 beside FP16 subnormal mean values.  The stated bound
+    must hold for every emulated sum, and the purely relative part alone must
+    fail on some of them (so the absolute term is what carries them)."""
+    rng = np.random.default_rng(17)
+    relative_alone_fails = 0
+    for trial in range(240):
+        nt = int(rng.integers(1, 120))
+        case = trial % 3
+        if case == 0:        # mean values in FP32's subnormal range
+            v = (rng.uniform(0.01, 1, nt) / np.sqrt(nt)).astype(np.float32)
+            u = 10.0 ** rng.uniform(-45, -37, nt)
+        elif case == 1:      # tiny object values: products underflow
+            v = (10.0 ** rng.uniform(-30, -20, nt)).astype(np.float32)
+            u = 10.0 ** rng.uniform(-25, -5, nt)
+        else:                # large object values, mean values below FP16's normal range
+            v = rng.uniform(0.5, 50.0, nt).astype(np.float32)
+            u = 10.0 ** rng.uniform(-9, -4.3, nt)
+        u = u.astype(np.float64)
+        acc = _emulate(vt, v, u, fused)
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
+        c, a, _ = ivf.cert_bound(vt, nt, float(v.max()))
+        err = abs(Fraction(float(acc)) - exact)
+        assert err <= Fraction(c) * exact + Fraction(a), (vt, trial, float(err), float(exact))
+        relative_alone_fails += err > Fraction(c) * exact
+    assert relative_alone_fails > 0
 
 
 def test_batch_build_rejects_bad_arguments_before_any_launch():
@@ -203,19 +260,21 @@ def test_fixed_point_bound_holds_for_emulated_ivfd_scores(below):
         assert q < 2 ** 32
         got = Fraction(float(np.float32(q))) / Fraction(2) ** F
         exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
-        c, a, g = ivf.cert_bound_fixed(nt, 2.0 ** F)
+        c, a, g = ivf.cert_bound_fixed(nt, 2.0 ** F, float(v.max()))
         err = abs(got - exact)
         assert err <= Fraction(c) * exact + Fraction(a), (F, trial, float(err), float(exact))
 
 
 def test_fixed_point_constants_and_arguments():
-    c, a, g = ivf.cert_bound_fixed(100, 2.0 ** 30)
+    c, a, g = ivf.cert_bound_fixed(100, 2.0 ** 30, 3.0)
     u = Fraction(1, 2 ** 24)
     assert c >= float(((1 + u) ** 3 - 1) * Fraction(101, 100))
-    assert a >= 100 * (0.5 / 2 ** 30) * 1.01
+    assert a >= 100 * (0.5 / 2 ** 30 + 4.0 * 2.0 ** -126) * 1.01
     assert g >= float(_exact_gamma(100, Fraction(1, 2 ** 53)))
     lib = _lib.get()
     out = (ctypes.c_double * 3)()
-    assert lib.ivf_cert_bound_fixed(-1, 1.0, out) == -1
-    assert lib.ivf_cert_bound_fixed(5, 0.0, out) == -1
-    assert lib.ivf_cert_bound_fixed(5, float("inf"), out) == -1
+    assert lib.ivf_cert_bound_fixed(-1, 1.0, 1.0, out) == -1
+    assert lib.ivf_cert_bound_fixed(5, 0.0, 1.0, out) == -1
+    assert lib.ivf_cert_bound_fixed(5, float("inf"), 1.0, out) == -1
+    assert lib.ivf_cert_bound_fixed(5, 1.0, -1.0, out) == -1
+    assert lib.ivf_cert_bound(0, 5, float("nan"), out) == -1

@@ -85,17 +85,63 @@ def test_trace_summary_lists_launches_and_the_steady_state_average(tmp_path):
 
 
 def test_algorithmic_bytes_and_the_stale_counter_rule(tmp_path, monkeypatch):
-    # 8 B per FP32 posting entry (id + value), 4 B for 16-bit values; 16 B per
-    # object nonzero; 8 B per row pointer
-    assert bench.walk_bytes(10, 3, 2, "f32") == 80 + 48 + 24
-    assert bench.walk_bytes(10, 3, 2, "bf16") == 40 + 48 + 24
-    assert bench.iteration_bytes(10, 3, 2, 5, "f32") == bench.walk_bytes(10, 3, 2, "f32") + 16 + 48 + 5 * 32
+    # 8 B per FP32 posting entry (id + value), 4 B for 16-bit values; per
+    # cluster range: 24 B per object nonzero (id, value, slice descriptor),
+    # 8 B per row pointer, 16 B per range record written
+    assert bench.walk_bytes(10, 3, 2, 1, "f32") == 80 + 72 + 24 + 32
+    assert bench.walk_bytes(10, 3, 2, 4, "bf16") == 40 + 4 * (72 + 24 + 32)
+    assert (bench.iteration_bytes(10, 3, 2, 1, 5, "f32")
+            == bench.walk_bytes(10, 3, 2, 1, "f32") + 16 + 48 + 5 * 32)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "profiles")
     monkeypatch.setattr(bench, "kernel_hash", lambda sources=("assign.hip", "update.hip"): "abc")
-    p = tmp_path / "profiles" / "walk_w_f32_traffic.json"
-    p.write_text(json.dumps({"kernel_hash": "abc", "hbm_bytes_per_launch": 123.0}))
-    assert bench.measured_traffic("w", "f32", None) == 123.0
-    p.write_text(json.dumps({"kernel_hash": "old", "hbm_bytes_per_launch": 123.0}))
-    assert bench.measured_traffic("w", "f32", None) is None      # counters of another kernel
-    assert bench.measured_traffic("w", "bf16", None) is None     # none taken
+    p = tmp_path / "profiles" / "walk_w_f32_levels.json"
+    p.write_text(json.dumps({"kernel_hash": "abc", "l2_read_bytes": 123.0}))
+    assert bench.level_counters("k_walk", "w", "f32")["l2_read_bytes"] == 123.0
+    p.write_text(json.dumps({"kernel_hash": "old", "l2_read_bytes": 123.0}))
+    assert bench.level_counters("k_walk", "w", "f32") is None     # counters of another kernel
+    assert bench.level_counters("k_walk", "w", "bf16") is None    # none taken
+
+
+PROBE = "ivf::(anonymous namespace)::k_read(uint4 const*, long, long, long, int, int, uint4*)"
+
+
+def test_level_summary_scales_requests_by_the_probes(tmp_path, monkeypatch):
+    """Requests are turned into bytes by what the same counter reads for the
+    timed probe of known size; the walk's last dispatch is the one used."""
+    cus = 4
+    l2 = bench.probe_bytes("l2", cus)
+    hbm = bench.probe_bytes("hbm", cus)
+    rows = []
+    did = 0
+    # probes: (warm, timed) per level; 128-byte L1->L2 requests, 64-byte fabric ones
+    for level in bench.CEILINGS:
+        for _ in range(2):
+            nb = bench.probe_bytes(level, cus)
+            for name, v in (("TCP_TCC_READ_REQ_sum", nb / 128), ("TCC_EA0_RDREQ_sum", nb / 64),
+                            ("TCC_HIT_sum", 1.0), ("TCC_MISS_sum", 1.0)):
+                rows.append({"Dispatch_Id": did, "Kernel_Name": PROBE, "Counter_Name": name,
+                             "Counter_Value": v})
+            did += 1
+    for walk_req in (10.0, 1000.0):        # two walk launches: the last one counts
+        for name, v in (("TCP_TCC_READ_REQ_sum", walk_req), ("TCC_EA0_RDREQ_sum", walk_req / 4),
+                        ("TCC_HIT_sum", 3.0), ("TCC_MISS_sum", 1.0)):
+            rows.append({"Dispatch_Id": did, "Kernel_Name": WALK, "Counter_Name": name,
+                         "Counter_Value": v})
+        did += 1
+    _write(tmp_path / "p.csv", ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+           rows)
+    out = bench.summarize_levels("w", "f32", str(tmp_path / "l.json"), str(tmp_path / "l.txt"),
+                                 "cmd", "k_walk", cus, str(tmp_path / "p.csv"))
+    assert out["l2_bytes_per_request"] == pytest.approx(128.0)
+    assert out["fabric_bytes_per_request"] == pytest.approx(64.0)
+    assert out["l2_read_bytes"] == pytest.approx(1000.0 * 128)
+    assert out["fabric_read_bytes"] == pytest.approx(250.0 * 64)
+    assert out["l2_hit_rate"] == pytest.approx(0.75)
+    assert l2 < hbm
+    # the roofline then divides by the walk time and the measured ceilings
+    monkeypatch.setattr(bench, "level_counters", lambda *a: out)
+    r = bench.walk_roofline("k_walk", "w", "f32", 2.0, 1e6, {"l2": 1e-4, "infinity_cache": 1e-4,
+                                                             "hbm": 1e-4}, 1.0, 1.0)
+    assert r["bound"] == "l2" and r["frac"] == pytest.approx(1000.0 * 128 / 2.0 / 1e9 / 1e-4)
+    assert r["effective_gbps_algorithmic"] == pytest.approx(1e6 / 2.0 / 1e9)

@@ -145,3 +145,77 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(ivf.IvfError):
         b.set_slack(-1.0, 0)
     b.close()
+
+
+def test_batch_at_the_many_instance_workload_scale():
+    """24 instances of the 96-instance workload (uneven N up to 400,000, k up
+    to the workload's largest, one object set's 8 restarts) for 5 iterations:
+    2 eager, then graph replays.  Every instance's assignment vector and
+    counters at every iteration, and its final means, equal a single
+    handle's bit for bit; at every iteration each single handle's FP64
+    re-scored objects are re-assigned identically by the oracle from the
+    same means, so the batch's are too."""
+    from gpu_util import digest, oracle_check
+    allinst = datagen.batched_instances()
+    distinct = [i for i, (w, r) in enumerate(allinst) if w.name < "batch48"]
+    restarted_sets = sorted({w.name for w, r in allinst if w.name >= "batch48"},
+                            key=lambda nm: -[w.k for w, _ in allinst if w.name == nm][0])
+    chosen = [i for i, (w, r) in enumerate(allinst) if w.name == restarted_sets[0]]
+    by_k = sorted(distinct, key=lambda i: allinst[i][0].k)
+    chosen.append(by_k[-1])                                   # the largest k
+    rest = by_k[:-1]
+    chosen += [rest[int(round(q * (len(rest) - 1) / 14))] for q in range(15)]
+    assert len(set(chosen)) == 24
+    inst = [allinst[i] for i in chosen]
+    data = {}
+    for w, _ in inst:
+        if w.name not in data:
+            x = w.generate()
+            data[w.name] = (x, to_dev(x))
+    print("instances", [(w.name, w.n, w.k, r) for w, r in inst], flush=True)
+    b = ivf.IVFBatch([(*data[w.name][1], w.d) for w, _ in inst], [w.k for w, _ in inst])
+    seeds = [w.seeds(data[w.name][0], restart=r) for w, r in inst]
+    b.init_seeds([i32(s) for s in seeds])
+    ba = [i32(np.full(w.n, -1, np.int32)) for w, _ in inst]
+    iters = 5
+    hist = []
+    for r in range(iters):
+        bst = b.iterate(1, ba)[0]
+        hist.append([(digest(ba[i].cpu().numpy()), bst[i]) for i in range(len(inst))])
+        print("batch iteration", r + 1, "plan", b.plan, flush=True)
+        torch.cuda.synchronize()
+    assert b.plan["graphs"] == 1 and b.plan["captures"] >= 1
+    final = [tuple(t.cpu().numpy() for t in b.get_means(i)) for i in range(len(inst))]
+    b.close()
+    checked = 0
+    for i, (w, rs) in enumerate(inst):
+        x, dx = data[w.name]
+        km = ivf.IVFKMeans(*dx, w.d, w.k)
+        km.init_seeds(i32(seeds[i]))
+        sa = i32(np.full(w.n, -1, np.int32))
+        prev = np.full(w.n, -1, np.int32)
+        for r in range(iters):
+            means = means_to_host(*km.get_means(), w.k, w.d)
+            s1 = km.assign(sa)
+            got = sa.cpu().numpy()
+            h, bs = hist[r][i]
+            assert digest(got) == h, (w.name, rs, r)
+            for key in ("changed", "mult_adds", "certified", "rescored", "zero_overlap"):
+                assert bs[key] == s1[key], (w.name, rs, r, key)
+            assert bs["objective"] == s1["objective"]
+            flags = km.get_scores()[4].cpu().numpy()
+            resc = np.nonzero(flags & 2)[0]
+            if len(resc):
+                _, mism = oracle_check(x, means, prev, got, resc)
+                assert len(mism) == 0, (w.name, rs, r, mism[:10])
+                checked += len(resc)
+            s2 = km.update(sa)
+            for key in ("objective_exact", "empty_clusters", "nnz_means"):
+                assert bs[key] == s2[key], (w.name, rs, r, key)
+            prev = got
+        sp, si, sv = (t.cpu().numpy() for t in km.get_means())
+        bp, bi, bv = final[i]
+        assert np.array_equal(bp, sp) and np.array_equal(bi, si) and np.array_equal(bv, sv)
+        km.close()
+    print("re-scored objects checked against the oracle:", checked, flush=True)
+    assert checked > 0

@@ -1,7 +1,12 @@
-"""The GPU's own Lloyd chain against the oracle's stored chain on the
-300,000-document x 100,000-term workload with k = 10,000 (20 iterations).
+"""The GPU's own Lloyd chain against the oracle's stored chains:
+  - nyt_like: 300,000 documents x 100,000 terms, k = 10,000, 20 iterations
+    (NYT-like density; this chain reaches a fixed point at iteration 2);
+  - pubmed_1m: 1,000,000 documents x 140,000 terms, k = 10,000, 10 iterations
+    (the paper's 1M-document PubMed sample shape; hundreds of thousands of
+    objects still move after the first iterations, so every iteration checks
+    a new state).
 
-tests/golden/nyt_like_chain.json was written by make_chain_golden.py, which
+tests/golden/<workload>_chain.json was written by make_chain_golden.py, which
 calls only the input generator and the FP64 oracle.  Per iteration the GPU
 chain (its own means, no injection) must give the identical assignment vector
 (SHA-256), the same mult-add count (Eq. ivf_mult), change count, zero-overlap
@@ -25,11 +30,12 @@ if not torch.cuda.is_available():
 import paper_2002_09094_amd as ivf  # noqa: E402
 from gpu_util import i32, to_dev  # noqa: E402
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "nyt_like_chain.json")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def test_nyt_like_chain_matches_oracle_golden():
-    g = json.load(open(GOLDEN))
+@pytest.mark.parametrize("workload", ["nyt_like", "pubmed_1m"])
+def test_chain_matches_oracle_golden(workload):
+    g = json.load(open(os.path.join(GOLDEN, workload + "_chain.json")))
     w = datagen.WORKLOADS[g["workload"]]
     print("generating", w.name, flush=True)
     x = w.generate()

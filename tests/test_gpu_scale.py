@@ -1,10 +1,22 @@
-"""GPU parity at the benchmark sizes, on sampled outputs the oracle computes
-one by one, plus properties of the GPU's own chain that hold at any size.
+"""GPU parity at the benchmark sizes: the GPU's own Lloyd chain from the
+seeded initial state, in the launch configuration bench.py times, checked
+against the FP64 oracle at every iteration.
 
-The means handed to both sides come from the oracle: its update step applied
-to a seeded random partition (the shape of steady-state means on this
-structureless data).  The GPU walk then assigns all objects in the launch
-configuration bench.py times; the oracle assigns a seeded sample of them.
+Per iteration the means the GPU assigned with are copied to the host, and the
+oracle assigns, from the same previous assignment,
+  - every object the GPU re-scored in FP64 (its FP32 margin was inside the
+    certification bound),
+  - the objects with the smallest FP32 margin (best - second) / best,
+  - a seeded sample;
+the GPU's assignment must be identical on all of them.  Every other object
+was certified: its FP32 winner is provably the oracle's argmax.  The same
+chain with BF16 and FP16 mean values must give the identical assignment
+vector (SHA-256) at every iteration, re-scoring some objects in FP64.  The
+multiplication count M must equal sum_t (no)_t (nc)_t exactly (Eq. ivf_mult).
+
+Workloads: 8M documents x 140k terms at k = 10,000 (the benchmark's), and the
+precision workload, 2M documents x 200k terms at k = 50,000 (40+ cluster
+ranges).  Measured numbers are also written as JSON into $IVF_REPORT_DIR.
 """
 import json
 import os
@@ -22,10 +34,11 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2002_09094_amd as ivf  # noqa: E402
-from gpu_util import DEV, i32, means_to_dev, to_dev  # noqa: E402
+from gpu_util import (digest, i32, means_to_host, oracle_check, score_errors,  # noqa: E402
+                      to_dev, uncertain_objects)
 
-# measured numbers are also written as JSON files into $IVF_REPORT_DIR, if set
 REPORT_DIR = os.environ.get("IVF_REPORT_DIR", "")
+VALTYPES = ("f32", "bf16", "f16")
 
 
 def _report(name, payload):
@@ -35,64 +48,85 @@ def _report(name, payload):
             json.dump(payload, f, indent=1)
 
 
-def _partition_means(x, k, seed):
-    labels = datagen.uniform_labels(x.n, k, seed, stream=11)
-    means, _ = oracle.update(x, k, labels, None)
-    return means
-
-
-def _sample(n, m, seed):
-    return np.sort(datagen.perm_prefix(n, m, seed, stream=7))
+def _chains_against_oracle(w, x, iters, n_margin, n_sample):
+    """FP32, BF16 and FP16 handles advanced in lockstep from the seeds; the FP32
+    chain's uncertain objects and a sample checked against the oracle at every
+    iteration, the 16-bit chains' assignments compared with FP32's."""
+    dx = to_dev(x)
+    kms = {vt: ivf.IVFKMeans(*dx, w.d, w.k, valtype=vt) for vt in VALTYPES}
+    seeds = i32(w.seeds(x))
+    for km in kms.values():
+        km.init_seeds(seeds)
+    a = {vt: i32(np.full(x.n, -1, np.int32)) for vt in VALTYPES}
+    prev = np.full(x.n, -1, np.int32)
+    vmax = float(x.values.max())
+    nmax = int(np.max(np.diff(x.indptr)))
+    rows, objs_hist = [], []
+    for r in range(iters):
+        means = means_to_host(*kms["f32"].get_means(), w.k, w.d)
+        no, nc = oracle.term_counts(x, means)
+        m_exact = int(np.sum(no * nc))
+        st, got, sc = {}, {}, {}
+        for vt in VALTYPES:
+            st[vt] = kms[vt].assign(a[vt])
+            got[vt] = a[vt].cpu().numpy()
+            sc[vt] = [t.cpu().numpy() for t in kms[vt].get_scores()]
+        best, best_id, second, _, flags = sc["f32"]
+        resc, low = uncertain_objects(best, second, flags, n_margin)
+        samp = np.sort(datagen.perm_prefix(x.n, n_sample, w.seed + 17 * r, stream=7))
+        objs = np.unique(np.concatenate([resc, low, samp]))
+        print("iteration %d: oracle on %d objects (%d re-scored, %d lowest margins, %d sampled)"
+              % (r + 1, len(objs), len(resc), len(low), len(samp)), flush=True)
+        ar, mism = oracle_check(x, means, prev, got["f32"], objs)
+        assert len(mism) == 0, (r, mism[:10])
+        row = {"iter": r + 1, "oracle_objects": int(len(objs)), "mult_adds": m_exact,
+               "nnz_means": means.nnz, "assign_sha256": digest(got["f32"])}
+        # the sample's rows of the oracle result, for the score errors
+        pos = np.searchsorted(objs, samp)
+        ar_s = oracle.AssignResult(ar.assign[pos], ar.rho[pos], ar.rho2[pos], 0.0, 0, 0, 0)
+        for vt in VALTYPES:
+            s = st[vt]
+            assert s["mult_adds"] == m_exact
+            assert s["certified"] + s["rescored"] + s["zero_overlap"] == x.n
+            assert digest(got[vt]) == row["assign_sha256"], (vt, r)
+            b, bi, s2, _, fl = sc[vt]
+            c, ab, g = ivf.cert_bound(vt, nmax, vmax)
+            e1, e2, n1, n2, held = score_errors(x, means, samp, ar_s, b, bi, s2, (c, ab, g))
+            assert held, (vt, r, e1, e2, c)
+            row[vt] = {"certified_fraction": s["certified"] / x.n, "rescored": s["rescored"],
+                       "changed": s["changed"], "walk_ms": s["walk_ms"],
+                       "max_rel_err_top1_sample": e1, "max_rel_err_top2_sample": e2,
+                       "sample_top1": n1, "sample_top2": n2,
+                       "max_rel_err_rescored": s["max_rel_err_rescored"], "bound_c": c}
+        rows.append(row)
+        objs_hist.append(objs)
+        for vt in VALTYPES:
+            su = kms[vt].update(a[vt])
+            assert su["objective_exact"] == pytest.approx(
+                st[vt]["objective"], rel=max(st[vt]["objective_bound"], 1e-12))
+            row[vt]["objective_exact"] = su["objective_exact"]
+        prev = got["f32"]
+    return kms, a, rows
 
 
 @pytest.fixture(scope="module")
 def pubmed():
     w = datagen.WORKLOADS["pubmed_8m"]
     print("generating pubmed_8m", flush=True)
-    x = w.generate()
-    means = _partition_means(x, w.k, w.seed)
-    return w, x, means
+    return w, w.generate()
 
 
-def test_pubmed_8m_sampled_parity_and_exact_count(pubmed):
-    w, x, means = pubmed
-    km = ivf.IVFKMeans(*to_dev(x), w.d, w.k)
-    km.set_means(*means_to_dev(means))
-    a = i32(np.full(x.n, -1, np.int32))
-    st = km.assign(a)
-    ga = a.cpu().numpy()
-    no, nc = oracle.term_counts(x, means)
-    assert st["mult_adds"] == int(np.sum(no * nc))          # Eq. ivf_mult, exact
-    idx = _sample(x.n, 3000, 31)
-    xs = x.subset(idx)
-    ar = oracle.assign(xs, means, np.full(len(idx), -1, np.int32))
-    assert np.array_equal(ga[idx], ar.assign)
-    best, best_id, second, rho, flags = km.get_scores()
-    rho = rho.cpu().numpy()[idx]
-    np.testing.assert_allclose(rho, ar.rho, rtol=1e-5)        # FP32 scores of the winners
-    _report("pubmed_8m_sampled_parity", {
-        "sample": len(idx), "identical": int(np.sum(ga[idx] == ar.assign)),
-        "certified": st["certified"], "rescored": st["rescored"], "mult_adds": st["mult_adds"],
-        "walk_ms": st["walk_ms"],
-        "max_rel_err_winner": float(np.max(np.abs(rho - ar.rho) / ar.rho))})
-    km.close()
-
-
-def test_pubmed_8m_gpu_chain_properties(pubmed):
-    w, x, _ = pubmed
-    km = ivf.IVFKMeans(*to_dev(x), w.d, w.k)
-    km.init_seeds(i32(w.seeds(x)))
-    a = i32(np.full(x.n, -1, np.int32))
-    objs = []
-    for r in range(3):
-        sa = km.assign(a)
-        su = km.update(a)
-        assert su["objective_exact"] == pytest.approx(sa["objective"], rel=sa["objective_bound"])
-        objs.append(su["objective_exact"])
-        assert sa["certified"] + sa["rescored"] + sa["zero_overlap"] == x.n
+def test_pubmed_8m_chain_matches_oracle_on_every_uncertain_object(pubmed):
+    w, x = pubmed
+    kms, a, rows = _chains_against_oracle(w, x, 3, 20_000, 50_000)
+    objs = [r["f32"]["objective_exact"] for r in rows]
     assert objs == sorted(objs)                           # non-decreasing objective
-    ptr, idx, val = (t.cpu().numpy() for t in km.get_means())
-    ga = a.cpu().numpy()
+    for vt in ("bf16", "f16"):
+        assert sum(r[vt]["rescored"] for r in rows) > 0
+    # the means: unit norm, supports = union of the members', values = the
+    # normalised member sums
+    ptr, idx, val = (t.cpu().numpy() for t in kms["f32"].get_means())
+    ga = a["f32"].cpu().numpy()
     rng = np.random.default_rng(5)
     for j in rng.choice(w.k, 20, replace=False):
         lo, hi = int(ptr[j]), int(ptr[j + 1])
@@ -102,67 +136,25 @@ def test_pubmed_8m_gpu_chain_properties(pubmed):
         if len(mem):
             sup = np.unique(np.concatenate([x.row(i)[0] for i in mem]))
             assert np.array_equal(sup, idx[lo:hi])
-            # the mean is the normalised member sum (member sum in FP64 here)
             s = np.zeros(w.d)
             for i in mem:
                 t, v = x.row(i)
                 s[t] += v.astype(np.float64)
             u = s / np.linalg.norm(s)
             np.testing.assert_allclose(val[lo:hi], u[idx[lo:hi]], rtol=1e-12)
-    km.close()
+    for km in kms.values():
+        km.close()
+    _report("pubmed_8m_chain_parity", {"workload": w.name, "n": x.n, "k": w.k, "iters": rows})
 
 
-@pytest.mark.parametrize("valtype", ["f32", "bf16", "f16"])
-def test_precision_workload_sampled(valtype):
+def test_precision_workload_chain_matches_oracle():
     w = datagen.WORKLOADS["precision"]
-    x = _precision_data()
-    means = _precision_means()
-    km = ivf.IVFKMeans(*to_dev(x), w.d, w.k, valtype=valtype)
-    km.set_means(*means_to_dev(means))
-    a = i32(np.full(x.n, -1, np.int32))
-    st = km.assign(a)
-    ga = a.cpu().numpy()
-    best, best_id, second, rho, flags = (t.cpu().numpy() for t in km.get_scores())
-    idx = _sample(x.n, 2000, 41)
-    xs = x.subset(idx)
-    ar = oracle.assign(xs, means, np.full(len(idx), -1, np.int32))
-    assert np.array_equal(ga[idx], ar.assign)
-    # tile-score error against the FP64 scores of the same clusters
-    bi = best_id[idx]
-    ok = bi >= 0
-    r64 = oracle.scores(x, means, idx[ok], bi[ok])
-    err1 = np.abs(best[idx][ok].astype(np.float64) - r64) / r64
-    c, _, g = ivf.cert_bound(valtype, int(np.max(np.diff(x.indptr))))
-    assert np.all(err1 <= c)
-    # top-2: where the tile's winner is the FP64 winner, the tile's best other
-    # score and the oracle's are maxima over the same clusters, so they agree
-    # within the same bound (plus the FP64 reference's own rounding)
-    same = (bi == ar.assign) & (ar.rho2 > 0)
-    err2 = np.abs(second[idx][same].astype(np.float64) - ar.rho2[same]) / ar.rho2[same]
-    assert same.sum() > 0.9 * len(idx) and np.all(err2 <= c + 2 * g)
-    _report("precision_%s" % valtype, {
-        "valtype": valtype, "n": x.n, "k": w.k, "sample": len(idx),
-        "identical_sample": int(np.sum(ga[idx] == ar.assign)),
-        "certified_fraction": st["certified"] / x.n, "rescored": st["rescored"],
-        "zero_overlap": st["zero_overlap"], "walk_ms": st["walk_ms"],
-        "assign_ms": st["assign_ms"], "mult_adds": st["mult_adds"],
-        "max_rel_err_top1_sample": float(err1.max()),
-        "max_rel_err_top2_sample": float(err2.max()),
-        "max_rel_err_rescored_winners": st["max_rel_err"], "plan": km.plan})
-    km.close()
-
-
-_PREC = {}
-
-
-def _precision_data():
-    if "x" not in _PREC:
-        _PREC["x"] = datagen.WORKLOADS["precision"].generate()
-    return _PREC["x"]
-
-
-def _precision_means():
-    if "m" not in _PREC:
-        w = datagen.WORKLOADS["precision"]
-        _PREC["m"] = _partition_means(_precision_data(), w.k, w.seed)
-    return _PREC["m"]
+    print("generating precision", flush=True)
+    x = w.generate()
+    kms, a, rows = _chains_against_oracle(w, x, 3, 20_000, 20_000)
+    assert kms["f32"].plan["ranges"] >= 40
+    for vt in ("bf16", "f16"):
+        assert sum(r[vt]["rescored"] for r in rows) > 0
+    for km in kms.values():
+        km.close()
+    _report("precision_chain_parity", {"workload": w.name, "n": x.n, "k": w.k, "iters": rows})

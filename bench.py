@@ -53,7 +53,7 @@ def iteration_bytes(m, nnz, n, ranges, nnz_means, valtype):
             + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
 
 
-def kernel_hash(sources=("assign.hip", "update.hip")):
+def kernel_hash(sources=("assign.hip", "invfile.hip")):
     """Hash of a kernel's sources and the shared headers: the walk's kernels
     and the inverted-file layout they read (slabs, postings) by default."""
     h = hashlib.sha256()
@@ -69,36 +69,46 @@ def kernel_hash(sources=("assign.hip", "update.hip")):
 # beyond the L2s, inside the 256 MB Infinity Cache; 4 GiB: HBM).
 CEILINGS = {"l2": (2 << 20, 0, 40), "infinity_cache": (128 << 20, 1, 100),
             "hbm": (4 << 30, 1, 3)}
-PROBE_WORKGROUPS_PER_CU = 8
+# Launch shapes each level is timed with, (loads in flight per lane,
+# workgroups per CU); a level's ceiling is the best of them.  The first shape
+# is also the one whose counters calibrate bytes per request.
+PROBE_SHAPES = [(4, 8), (8, 8), (16, 8), (4, 16), (8, 16), (16, 16)]
 
 
-def probe_bytes(level, cus):
+def probe_bytes(level, cus, wgs_per_cu=PROBE_SHAPES[0][1]):
     """Bytes one timed probe launch reads at `level`."""
     nbytes, mode, passes = CEILINGS[level]
     n16 = nbytes // 16
     if mode == 0:
-        return cus * PROBE_WORKGROUPS_PER_CU * n16 * 16 * passes
+        return cus * wgs_per_cu * n16 * 16 * passes
     return n16 * 16 * passes
 
 
 def read_ceilings():
     """Measured read bandwidth (GB/s) of working sets resident in L2, in the
     Infinity Cache and in HBM: the roofs the walk's counted traffic is placed
-    against (the library's streaming read probe, one warm-up and one timed
-    launch each)."""
+    against.  Each level is read by the library's streaming probe in every
+    shape of PROBE_SHAPES (one warm-up and one timed launch each) and takes
+    the best.  Returns (ceilings, per-shape rates)."""
     import torch
 
     import paper_2002_09094_amd as ivf
 
-    out = {}
+    out, shapes = {}, {}
     for level, (nbytes, mode, passes) in CEILINGS.items():
         buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
         torch.cuda.synchronize()
-        out[level] = ivf.read_ceiling(buf, mode, passes)
+        rates = [ivf.read_ceiling(buf, mode, passes, unroll=u, wgs_per_cu=w)
+                 for u, w in PROBE_SHAPES]
+        shapes[level] = {"%dx%d" % sh: r for sh, r in zip(PROBE_SHAPES, rates)}
+        out[level] = max(rates)
         del buf
     torch.cuda.empty_cache()
-    log("read ceilings (GB/s): " + ", ".join("%s %.0f" % kv for kv in out.items()))
-    return out
+    log("read ceilings (GB/s, best of %d shapes): " % len(PROBE_SHAPES)
+        + ", ".join("%s %.0f" % kv for kv in out.items()))
+    log("per shape (loads in flight x workgroups per CU): %s" % json.dumps(
+        {k: {s: round(r) for s, r in v.items()} for k, v in shapes.items()}))
+    return out, shapes
 
 
 def level_counters(kernel, workload, valtype):
@@ -116,7 +126,22 @@ def level_counters(kernel, workload, valtype):
     return t
 
 
-def walk_roofline(kernel, workload, valtype, walk_s, alg_bytes, ceilings, copy_gbps, add_gbps):
+def traffic_counters(kernel, workload, valtype):
+    """Calibrated FETCH_SIZE / WRITE_SIZE bytes per launch of `kernel`, from the
+    committed counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.json"
+                        % (kernel.replace("k_", ""), workload, valtype))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash(KERNEL_SOURCE[kernel]):
+        return None
+    return t
+
+
+def walk_roofline(kernel, workload, valtype, walk_s, alg_bytes, ceilings, copy_gbps, add_gbps,
+                  probe_shapes=None):
     """The walk against the roof it hits.  The method's algorithmic bytes
     charge every posting read to memory (the paper's per-access model), but
     the caches serve most of them, so those bytes per second are reported as
@@ -130,7 +155,8 @@ def walk_roofline(kernel, workload, valtype, walk_s, alg_bytes, ceilings, copy_g
     out = {"kernel": kernel, "unit": "GB/s",
            "algorithmic_bytes_per_launch": alg_bytes,
            "effective_gbps_algorithmic": alg_bytes / walk_s / 1e9,
-           "ceilings_gbps": ceilings, "hbm_peak_published_gbps": HBM_PEAK_GBPS,
+           "ceilings_gbps": ceilings, "ceilings_by_probe_shape": probe_shapes,
+           "hbm_peak_published_gbps": HBM_PEAK_GBPS,
            "stream_copy_gbps": copy_gbps, "stream_add_gbps": add_gbps}
     lv = level_counters(kernel, workload, valtype)
     if lv is None:
@@ -142,14 +168,18 @@ def walk_roofline(kernel, workload, valtype, walk_s, alg_bytes, ceilings, copy_g
         "l2": (lv["l2_read_bytes"] / walk_s / 1e9, ceilings["l2"]),
         "infinity_cache": (lv["fabric_read_bytes"] / walk_s / 1e9, ceilings["infinity_cache"]),
     }
+    tr = traffic_counters(kernel, workload, valtype)
+    write_bytes = tr["write_bytes"] if tr else 0.0
     fr = {k: a / p for k, (a, p) in levels.items()}
     bound = max(fr, key=fr.get)
     a, p = levels[bound]
     out.update({
         "bound": bound, "achieved": a, "peak": p, "frac": a / p,
         "peak_kind": "measured read ceiling of a working set resident at that level",
-        "traffic": lv["fabric_read_bytes"] + lv.get("write_bytes", 0.0),
-        "traffic_unit": "bytes per launch between L2 and the memory side (reads + writes)",
+        "traffic": lv["fabric_read_bytes"] + write_bytes,
+        "traffic_unit": ("bytes per launch between L2 and the memory side: reads (counted "
+                         "requests) + writes (calibrated WRITE_SIZE)" if write_bytes else
+                         "bytes per launch read by L2 from the memory side"),
         "levels": {k: {"achieved": a_, "peak": p_, "frac": a_ / p_}
                    for k, (a_, p_) in levels.items()},
         "hbm_upper_bound": {"achieved": lv["fabric_read_bytes"] / walk_s / 1e9,
@@ -349,7 +379,8 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         f.write("\n".join(lines) + "\n")
 
 
-KERNEL_SOURCE = {"k_walk": ("assign.hip", "update.hip"), "k_walk_batch": ("assign.hip", "update.hip"),
+KERNEL_SOURCE = {"k_walk": ("assign.hip", "invfile.hip"),
+                 "k_walk_batch": ("assign.hip", "invfile.hip"),
                  "k_ivfd_walk": ("ivfd.hip",)}
 
 
@@ -366,7 +397,8 @@ def _last_dispatch_values(rows, match):
 def summarize_levels(workload, valtype, out_json, out_txt, command, kernel, cus, *csvs):
     """Bytes the walk moved at each level of the memory hierarchy, from
     rocprofv3 --pmc passes over a run that first times the read probes (three
-    levels, a warm-up and a timed launch each, in the order of CEILINGS) and
+    levels, a warm-up and a timed launch per shape of PROBE_SHAPES, in the
+    order of CEILINGS) and
     then the walk: L1 -> L2 read requests (TCP_TCC_READ_REQ_sum) and L2 ->
     fabric read requests (TCC_EA0_RDREQ_sum) of the last walk launch, each
     scaled to bytes by what the same counter reads for the timed probe of
@@ -387,8 +419,9 @@ def summarize_levels(workload, valtype, out_json, out_txt, command, kernel, cus,
     levels = list(CEILINGS)
 
     def timed_probe(counter, level):
+        # per level: (warm-up, timed) per shape; the first shape's timed launch
         vals = by_counter[counter]
-        return vals[2 * levels.index(level) + 1]
+        return vals[2 * len(PROBE_SHAPES) * levels.index(level) + 1]
 
     walk = {}
     for path in csvs:
@@ -406,8 +439,6 @@ def summarize_levels(workload, valtype, out_json, out_txt, command, kernel, cus,
     if "TCC_HIT_sum" in walk and "TCC_MISS_sum" in walk:
         h, m = walk["TCC_HIT_sum"], walk["TCC_MISS_sum"]
         out["l2_hit_rate"] = h / (h + m)
-    if "TCC_EA0_WRREQ_sum" in walk:
-        out["write_bytes"] = walk["TCC_EA0_WRREQ_sum"] * fab_bpr
     mf = [v for k, v in walk.items() if "MFMA" in k]
     out["mfma_instructions"] = sum(mf) if mf else None
     with open(out_json, "w") as f:
@@ -697,7 +728,7 @@ def run_batched(args):
     kr = plan["kr_max"]
     wb = [sum(walk_bytes(s["mult_adds"], data[w.name][0].nnz, w.n, -(-w.k // kr), args.valtype)
               for s, (w, _) in zip(st, inst)) for st in per]
-    ceilings = read_ceilings()
+    ceilings, probe_shapes = read_ceilings()
 
     # the state after the timed iterations, for the oracle leg: every
     # instance's means and assignment, then one more iteration
@@ -735,7 +766,8 @@ def run_batched(args):
         "certified_fraction": (sum(s["certified"] for st in per for s in st)
                                / (len(per) * sum(w.n for w, _ in inst))),
         "roofline": walk_roofline("k_walk_batch", "batched96", args.valtype, walk_avg_s,
-                                  sum(wb) / len(wb), ceilings, copy_gbps, add_gbps),
+                                  sum(wb) / len(wb), ceilings, copy_gbps, add_gbps,
+                                  probe_shapes),
     }
     b.close()
     if not args.no_cpu_baseline:
@@ -852,7 +884,7 @@ def run_single(args):
     if args.calibrate_copy:
         calibration_copies()
     copy_gbps, add_gbps = stream_gbps()
-    ceilings = read_ceilings()
+    ceilings, probe_shapes = read_ceilings()
     w = datagen.WORKLOADS[args.workload]
     log("generating %s: n=%d d=%d lambda=%g k=%d" % (w.name, w.n, w.d, w.lam, w.k))
     x = w.generate()
@@ -944,7 +976,8 @@ def run_single(args):
         "changed_per_step": [p[0]["changed"] for p in per],
         "objective": per[-1][1]["objective_exact"],
         "roofline": walk_roofline("k_walk", w.name, args.valtype, walk_avg_s,
-                                  sum(wb) / len(wb), ceilings, copy_gbps, add_gbps),
+                                  sum(wb) / len(wb), ceilings, copy_gbps, add_gbps,
+                                  probe_shapes),
     }
     km.close()
     del xd, a

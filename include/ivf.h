@@ -96,6 +96,10 @@ typedef struct {
                                range's clusters is stored as a dense slab (zeros for absent
                                clusters, no ids); 0: default 0.35; > 1: never dense */
     void* stream;           /* hipStream_t; NULL = the null stream */
+    int32_t full_update;    /* 1: every ivf_update runs the full reduction over all object
+                               entries; 0 (default): when few objects changed cluster since
+                               the previous update, only their entries are reduced and merged
+                               into the stored exact member sums (same result bit for bit) */
 } ivf_options;
 
 /* Fills *o with the defaults (F32, certify on, planner's choices, null stream). */
@@ -124,6 +128,9 @@ typedef struct {
     int64_t nnz_means;       /* sum_j (ntm)_j after the call */
     int64_t inexact_terms;   /* terms whose fixed-point member sums were rounded */
     float update_ms;         /* device time of the update step */
+    int64_t update_delta_entries; /* the update was incremental: object entries of the
+                                objects that changed cluster, reduced and merged into the
+                                stored sums; -1: the full reduction ran */
 } ivf_stats;
 
 /*
@@ -310,14 +317,16 @@ ivf_status ivf_cert_bound_fixed(int64_t nt, double scale, double vmax, double c[
  * traffic is placed.  mode 0: every workgroup reads the whole buffer (a few
  * MB stay resident in each L2); mode 1: the workgroups split the buffer and
  * sweep it `passes` times (a buffer between the L2s' and the Infinity
- * Cache's sizes is served by the latter, GBs by HBM).  One untimed launch
- * warms the caches, one launch is timed with HIP events on `stream`
- * (hipStream_t, NULL = null stream); *gbps receives bytes read / time in
- * GB/s.  Allocates and frees a small sink buffer; synchronises the stream.
- * IVF_ERR_ARG for bad arguments, IVF_ERR_HIP / IVF_ERR_OOM on HIP failures.
+ * Cache's sizes is served by the latter, GBs by HBM).  unroll (4, 8 or 16)
+ * loads per lane are in flight before any is used; wgs_per_cu (1 .. 32)
+ * workgroups of 256 threads per compute unit.  One untimed launch warms the
+ * caches, one launch is timed with HIP events on `stream` (hipStream_t, NULL
+ * = null stream); *gbps receives bytes read / time in GB/s.  Allocates and
+ * frees a small sink buffer; synchronises the stream.  IVF_ERR_ARG for bad
+ * arguments, IVF_ERR_HIP / IVF_ERR_OOM on HIP failures.
  */
 ivf_status ivf_read_ceiling(const void* buf, int64_t bytes, int32_t mode, int32_t passes,
-                            void* stream, double* gbps);
+                            int32_t unroll, int32_t wgs_per_cu, void* stream, double* gbps);
 
 /* Frees the handle and everything it owns (NULL is a no-op). */
 void ivf_destroy(ivf_handle* h);

@@ -38,7 +38,7 @@ def _need_cuda(t, dtype, name):
 
 
 def _options(valtype="f32", certify=True, cluster_range=0, waves_per_wg=0, objects_per_item=0,
-             force_rescore=False, dense_threshold=0.0, stream=None):
+             force_rescore=False, dense_threshold=0.0, stream=None, full_update=False):
     o = _lib.ivf_options()
     _lib.get().ivf_default_options(ctypes.byref(o))
     o.valtype = VALTYPES[valtype] if isinstance(valtype, str) else int(valtype)
@@ -49,6 +49,7 @@ def _options(valtype="f32", certify=True, cluster_range=0, waves_per_wg=0, objec
     o.force_rescore = 1 if force_rescore else 0
     o.dense_threshold = float(dense_threshold)
     o.stream = ctypes.c_void_p(stream) if stream else None
+    o.full_update = 1 if full_update else 0
     return o
 
 
@@ -79,10 +80,11 @@ def cert_bound_fixed(nt, scale, vmax=1.0):
     return tuple(c)
 
 
-def read_ceiling(buf, mode, passes, stream=None):
+def read_ceiling(buf, mode, passes, unroll=4, wgs_per_cu=8, stream=None):
     """Read bandwidth (GB/s) of a plain streaming read of the CUDA tensor `buf`
     (mode 0: every workgroup reads all of it; mode 1: split and swept
-    `passes` times): the measured roofs of the walk's traffic."""
+    `passes` times; `unroll` loads per lane in flight, `wgs_per_cu`
+    workgroups per compute unit): the measured roofs of the walk's traffic."""
     import torch
     if not isinstance(buf, torch.Tensor) or not buf.is_cuda or not buf.is_contiguous():
         raise TypeError("buf must be a contiguous CUDA tensor")
@@ -90,7 +92,8 @@ def read_ceiling(buf, mode, passes, stream=None):
         stream = torch.cuda.current_stream().cuda_stream
     out = ctypes.c_double()
     check(_lib.get().ivf_read_ceiling(_ptr(buf), buf.numel() * buf.element_size(), int(mode),
-                                      int(passes), ctypes.c_void_p(stream) if stream else None,
+                                      int(passes), int(unroll), int(wgs_per_cu),
+                                      ctypes.c_void_p(stream) if stream else None,
                                       ctypes.byref(out)))
     return out.value
 
@@ -105,7 +108,7 @@ class IVFKMeans:
 
     def __init__(self, indptr, indices, values, d, k, *, valtype="f32", certify=True,
                  cluster_range=0, waves_per_wg=0, objects_per_item=0, force_rescore=False,
-                 dense_threshold=0.0, stream=None):
+                 dense_threshold=0.0, stream=None, full_update=False):
         import torch
         _need_cuda(indptr, torch.int64, "indptr")
         _need_cuda(indices, torch.int32, "indices")
@@ -119,7 +122,7 @@ class IVFKMeans:
         self.nnz = indices.numel()
         x = _lib.ivf_csr(self.n, self.d, self.nnz, _ptr(indptr), _ptr(indices), _ptr(values))
         o = _options(valtype, certify, cluster_range, waves_per_wg, objects_per_item,
-                     force_rescore, dense_threshold, stream)
+                     force_rescore, dense_threshold, stream, full_update)
         h = ctypes.c_void_p()
         check(_lib.get().ivf_build(ctypes.byref(x), self.k, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -35,7 +35,7 @@ class ivf_options(ctypes.Structure):
     _fields_ = [("valtype", c_int32), ("certify", c_int32), ("cluster_range", c_int32),
                 ("waves_per_wg", c_int32), ("objects_per_item", c_int32),
                 ("force_rescore", c_int32), ("dense_threshold", c_float),
-                ("stream", c_void_p)]
+                ("stream", c_void_p), ("full_update", c_int32)]
 
 
 class ivf_stats(ctypes.Structure):
@@ -44,7 +44,8 @@ class ivf_stats(ctypes.Structure):
                 ("mult_adds", c_int64), ("max_rel_err_rescored", c_double),
                 ("assign_ms", c_float), ("walk_ms", c_float),
                 ("objective_exact", c_double), ("empty_clusters", c_int64),
-                ("nnz_means", c_int64), ("inexact_terms", c_int64), ("update_ms", c_float)]
+                ("nnz_means", c_int64), ("inexact_terms", c_int64), ("update_ms", c_float),
+                ("update_delta_entries", c_int64)]
 
     def to_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -70,8 +71,8 @@ SIGNATURES = {
     "ivf_cert_bound": (c_int32, [c_int32, c_int64, c_double, ctypes.POINTER(c_double)]),
     "ivf_cert_bound_fixed": (c_int32, [c_int64, c_double, c_double,
                                        ctypes.POINTER(c_double)]),
-    "ivf_read_ceiling": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_void_p,
-                                   ctypes.POINTER(c_double)]),
+    "ivf_read_ceiling": (c_int32, [c_void_p, c_int64, c_int32, c_int32, c_int32, c_int32,
+                                   c_void_p, ctypes.POINTER(c_double)]),
     "ivf_destroy": (None, [c_void_p]),
     "ivf_last_error": (ctypes.c_char_p, [c_void_p]),
     "ivf_status_str": (ctypes.c_char_p, [c_int32]),

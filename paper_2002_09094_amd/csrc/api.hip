@@ -13,6 +13,7 @@
 
 #include "ivf_internal.h"
 #include "kernels.h"
+#include "update.h"
 
 using namespace ivf;
 
@@ -179,6 +180,21 @@ struct ivf_handle {
     double* part = nullptr;
     double* dscal = nullptr;   // [0] objective, [1] exact objective
     Counters* cnt = nullptr;
+    // incremental update: the exact member sums of tab_assign, in (cluster,
+    // term) order (table tc; the other is the next update's output), and the
+    // merge's work arrays, sized with the tables
+    bool tab_valid = false;
+    int tc = 0;
+    int64_t tab_n = 0;
+    int64_t tab_cap[2] = {0, 0};
+    int32_t* tab_j[2] = {nullptr, nullptr};
+    int32_t* tab_t[2] = {nullptr, nullptr};
+    unsigned long long* tab_acc[2] = {nullptr, nullptr};
+    int64_t merge_cap = 0;
+    uint32_t* merge_add = nullptr;
+    int64_t* merge_cs = nullptr;
+    int32_t* tab_assign = nullptr;
+    int64_t* delta_off = nullptr;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     std::string err;
 };
@@ -217,6 +233,8 @@ void free_handle(ivf_handle* h) {
     dfree(h->rec); dfree(h->ivfd_rec); dfree(h->prev); dfree(h->seed_assign); dfree(h->rho); dfree(h->best);
     dfree(h->second); dfree(h->best_id); dfree(h->flags); dfree(h->rescore_list);
     dfree(h->part); dfree(h->dscal); dfree(h->cnt);
+    for (int b = 0; b < 2; ++b) { dfree(h->tab_j[b]); dfree(h->tab_t[b]); dfree(h->tab_acc[b]); }
+    dfree(h->merge_add); dfree(h->merge_cs); dfree(h->tab_assign); dfree(h->delta_off);
     for (auto& e : h->ev)
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
 }
@@ -292,6 +310,30 @@ ivf_status ensure_slab(ivf_handle* h, int64_t elems) {
     const int64_t cap = elems + elems / 4;
     HIPCHK(h, hipMalloc(&h->slab, (size_t)cap * (h->opt.valtype == IVF_VAL_F32 ? 4 : 2)));
     h->slab_cap = cap;
+    return IVF_OK;
+}
+
+// Table b of the incremental update grown to `need` entries (its content is
+// about to be overwritten), and the merge arrays to cover a table of `need`.
+ivf_status ensure_tab(ivf_handle* h, int b, int64_t need) {
+    need = std::max<int64_t>(need, 1);
+    if (need > h->tab_cap[b]) {
+        const int64_t cap = std::max<int64_t>(need, h->tab_cap[b] + h->tab_cap[b] / 4);
+        dfree(h->tab_j[b]); dfree(h->tab_t[b]); dfree(h->tab_acc[b]);
+        h->tab_cap[b] = 0;
+        HIPCHK(h, dalloc(&h->tab_j[b], cap));
+        HIPCHK(h, dalloc(&h->tab_t[b], cap));
+        HIPCHK(h, dalloc(&h->tab_acc[b], cap));
+        h->tab_cap[b] = cap;
+    }
+    if (need + 1 > h->merge_cap) {
+        const int64_t cap = std::max<int64_t>(need + 1, h->merge_cap + h->merge_cap / 4);
+        dfree(h->merge_add); dfree(h->merge_cs);
+        h->merge_cap = 0;
+        HIPCHK(h, dalloc(&h->merge_add, cap));
+        HIPCHK(h, dalloc(&h->merge_cs, cap));
+        h->merge_cap = cap;
+    }
     return IVF_OK;
 }
 
@@ -384,6 +426,10 @@ ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM, const int64_t* nnz_de
 // the inverted-file rebuild.  In fixed mode nothing synchronises or allocates.
 // clear = false keeps the assignment step's counters (the update only adds to
 // `empty` and `error_flags`, which the caller has cleared).
+// The incremental update is taken when the moved objects' entries are at most
+// this share of all object entries (else the full reduction is cheaper).
+constexpr int64_t kDeltaShare = 4;
+
 ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
                       bool clear = true) {
     const hipStream_t s = h->stream;
@@ -406,11 +452,55 @@ ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
     a.new_ptr = h->mm_ptr[nb];
     a.cnt = h->cnt;
     a.tmp = h->sc->tmp;
-    HIPCHK(h, launch_update_sums(a, s));
-    int64_t nnz_new = 0;
+    // The sums table serves single handles outside graph capture whose member
+    // sums are exact (no rounded term); it is valid again only once this
+    // update has completed.
+    const bool use_table = !h->fixed && h->owns_sc && !h->opt.full_update && h->ov->inexact == 0;
+    const bool had_table = h->tab_valid;
+    h->tab_valid = false;
+    int64_t delta = -1;   // delta entries of the incremental update; -1: full reduction
+    if (use_table && had_table) {
+        HIPCHK(h, h->sc->ensure(0, 0, h->n + 1, s));
+        if (!h->delta_off) HIPCHK(h, dalloc(&h->delta_off, h->n + 1));
+        HIPCHK(h, launch_delta_count(h->ov->x_ptr, h->n, assign, h->tab_assign, h->k,
+                                     h->delta_off, h->sc->tmp, s));
+        int64_t e = 0;
+        HIPCHK(h, hipMemcpyAsync(&e, h->delta_off + h->n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                                 s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        if (e >= 0 && e <= h->nnz / kDeltaShare) delta = e;
+    }
+    if (delta >= 0) {
+        const int nt = 1 - h->tc;
+        ivf_status st = ensure_tab(h, nt, h->tab_n + delta);
+        if (st != IVF_OK) return st;
+        DeltaArgs da{};
+        da.x_ptr = h->ov->x_ptr; da.x_idx = h->ov->x_idx; da.x_val = h->ov->x_val;
+        da.n = h->n; da.d = h->d; da.k = h->k;
+        da.assign = assign; da.old_assign = h->tab_assign;
+        da.off = h->delta_off; da.entries = delta;
+        da.shift = h->ov->shift; da.size = h->size; da.scal = h->scal;
+        da.keys = h->sc->keys; da.keys_alt = h->sc->keys_alt;
+        da.pay = h->sc->pay; da.pay_alt = reinterpret_cast<uint2*>(h->sc->seg_acc);
+        da.flag = h->sc->flag; da.segpos = h->sc->segpos;
+        da.dacc = h->sc->seg_acc; da.dj = h->sc->seg_j; da.dt = h->sc->seg_t;
+        da.ins = h->sc->vals; da.ins_lb = h->sc->vals_alt; da.ipos = h->sc->keys_alt;
+        da.tab_n = h->tab_n; da.cstart = h->cstart;
+        da.tab_j = h->tab_j[h->tc]; da.tab_t = h->tab_t[h->tc]; da.tab_acc = h->tab_acc[h->tc];
+        da.add = h->merge_add; da.cs = h->merge_cs;
+        da.new_j = h->tab_j[nt]; da.new_t = h->tab_t[nt]; da.new_acc = h->tab_acc[nt];
+        da.tmp = h->sc->tmp;
+        HIPCHK(h, launch_delta_update(da, s));
+        a.seg_acc = h->tab_acc[nt]; a.seg_j = h->tab_j[nt]; a.seg_t = h->tab_t[nt];
+        HIPCHK(h, launch_update_norms(a, s));
+    } else {
+        HIPCHK(h, launch_update_sums(a, s));
+    }
+    int64_t nnz_new = 0, segs = 0;
     if (!h->fixed) {
         HIPCHK(h, hipMemcpyAsync(&nnz_new, h->mm_ptr[nb] + h->k, sizeof(int64_t),
                                  hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipMemcpyAsync(&segs, h->scal + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
         ivf_status st = ensure_mm(h, nb, nnz_new);
         if (st != IVF_OK) return st;
@@ -421,8 +511,25 @@ ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
     a.new_row = h->mm_row[nb];
     HIPCHK(h, launch_update_fill(a, s));
     HIPCHK(h, launch_objective_exact(h->objpart, h->k, h->dscal + 1, s));
+    // the table of this update's sums, for the next one
+    if (delta >= 0) {
+        h->tc = 1 - h->tc;
+        h->tab_n = segs;
+    } else if (use_table) {
+        ivf_status st = ensure_tab(h, h->tc, segs);
+        if (st != IVF_OK) return st;
+        HIPCHK(h, launch_copy_table(h->sc->seg_j, h->sc->seg_t, h->sc->seg_acc, h->scal, segs,
+                                    h->tab_j[h->tc], h->tab_t[h->tc], h->tab_acc[h->tc], s));
+        h->tab_n = segs;
+    }
+    if (use_table) {
+        if (!h->tab_assign) HIPCHK(h, dalloc(&h->tab_assign, std::max<int64_t>(h->n, 1)));
+        HIPCHK(h, hipMemcpyAsync(h->tab_assign, assign, (size_t)h->n * sizeof(int32_t),
+                                 hipMemcpyDeviceToDevice, s));
+    }
     ivf_status st = rebuild_ivf(h, nb, nnz_new, h->fixed ? h->mm_ptr[nb] + h->k : nullptr);
     if (st != IVF_OK) return st;
+    h->tab_valid = use_table;
     h->cur = nb;
     h->nnzM = nnz_new;
     h->nnzM_known = !h->fixed;
@@ -441,6 +548,7 @@ ivf_status run_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats,
         stats->nnz_means = nnz_new;
         stats->inexact_terms = h->ov->inexact;
         stats->update_ms = ms;
+        stats->update_delta_entries = delta;
     }
     return IVF_OK;
 }
@@ -456,36 +564,51 @@ WalkArgs walk_args(ivf_handle* h) {
     return w;
 }
 
+// Per-call scratch of an assignment step: the previous assignment, the walk's
+// range records [n * R] and the FP64 re-score queue [n].  The handle's own
+// buffers, or another fixed set of the same sizes.
+struct AssignBufs {
+    int32_t* prev;
+    RangeRec* rec;
+    int32_t* rescore_list;
+};
+
+AssignBufs handle_bufs(ivf_handle* h) { return AssignBufs{h->prev, h->rec, h->rescore_list}; }
+
 // Assignment step after the walk: merge, FP64 re-score, objective.  R: the
 // range records per object (0: the plan's cluster ranges).
 // R, rec, fixed_scale: records of another walk (IVFD's, R per object, of
 // fixed-point sums at that scale); 0 / null: the plan's cluster ranges.
+// bufs: the step's per-call scratch (null: the handle's buffers).
 ivf_status assign_finish(ivf_handle* h, int32_t* assign, int32_t R = 0,
-                         const RangeRec* rec = nullptr, double fixed_scale = 0.0) {
+                         const RangeRec* rec = nullptr, double fixed_scale = 0.0,
+                         const AssignBufs* bufs = nullptr) {
     const hipStream_t s = h->stream;
     const Plan& p = h->plan;
+    const AssignBufs b = bufs ? *bufs : handle_bufs(h);
     MergeArgs m{};
     m.x_ptr = h->ov->x_ptr; m.n = h->n; m.R = R > 0 ? R : p.R;
     m.valtype = h->opt.valtype; m.certify = h->opt.certify; m.force_rescore = h->opt.force_rescore;
     m.fixed_scale = fixed_scale;
     m.vmax = h->ov->vmax;
-    m.rec = rec ? rec : h->rec; m.prev = h->prev; m.assign = assign; m.rho = h->rho;
+    m.rec = rec ? rec : b.rec; m.prev = b.prev; m.assign = assign; m.rho = h->rho;
     m.best = h->best; m.best_id = h->best_id; m.second = h->second; m.flags = h->flags;
-    m.rescore_list = h->rescore_list; m.cnt = h->cnt;
+    m.rescore_list = b.rescore_list; m.cnt = h->cnt;
     HIPCHK(h, launch_merge(m, s));
     if (h->opt.certify) {
         RescoreArgs r{};
         r.w = walk_args(h);
+        r.w.rec = b.rec;
         r.mm_ptr = h->mm_ptr[h->cur]; r.mm_idx = h->mm_idx[h->cur]; r.mm_val = h->mm_val[h->cur];
         r.valtype = h->opt.valtype;
         r.fixed_scale = fixed_scale;
         r.vmax = h->ov->vmax;
-        r.rec = rec ? nullptr : h->rec;   // another walk's records bound other ranges
-        r.rescore_list = h->rescore_list; r.prev = h->prev; r.assign = assign; r.rho = h->rho;
+        r.rec = rec ? nullptr : b.rec;   // another walk's records bound other ranges
+        r.rescore_list = b.rescore_list; r.prev = b.prev; r.assign = assign; r.rho = h->rho;
         r.best = h->best; r.best_id = h->best_id; r.cnt = h->cnt;
         HIPCHK(h, launch_rescore(r, h->rescore_waves, h->rescore_grid, s));
     }
-    HIPCHK(h, launch_objective(h->rho, assign, h->prev, h->n, h->part, kObjBlocks, h->dscal,
+    HIPCHK(h, launch_objective(h->rho, assign, b.prev, h->n, h->part, kObjBlocks, h->dscal,
                                h->cnt, s));
     return IVF_OK;
 }
@@ -518,6 +641,7 @@ ivf_status assign_stats(ivf_handle* h, ivf_stats* stats, bool timed) {
     stats->nnz_means = h->nnzM_known ? h->nnzM : -1;
     stats->inexact_terms = h->ov->inexact;
     stats->update_ms = 0.f;
+    stats->update_delta_entries = -1;
     return IVF_OK;
 }
 
@@ -1094,6 +1218,29 @@ __global__ void k_gather_flags(Counters* const* cnts, int32_t count, unsigned lo
     if (i < count) out[i] = cnts[i]->error_flags;
 }
 
+// The assignment step with its per-call scratch in `b`.
+ivf_status assign_with(ivf_handle* h, int32_t* assign, ivf_stats* stats, const AssignBufs& b) {
+    const hipStream_t s = h->stream;
+    const Plan& p = h->plan;
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[0], s));
+    HIPCHK(h, launch_clear_counters(h->cnt, s));
+    HIPCHK(h, hipMemcpyAsync(b.prev, assign, sizeof(int32_t) * (size_t)h->n,
+                             hipMemcpyDeviceToDevice, s));
+    WalkArgs w = walk_args(h);
+    w.rec = b.rec;
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[4], s));
+    HIPCHK(h, launch_walk(w, h->opt.valtype, p.waves, p.lds_bytes, h->walk_grid, s));
+    if (stats) HIPCHK(h, hipEventRecord(h->ev[5], s));
+    ivf_status st = assign_finish(h, assign, 0, nullptr, 0.0, &b);
+    if (st != IVF_OK) return st;
+    if (stats) {
+        HIPCHK(h, hipEventRecord(h->ev[1], s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        return assign_stats(h, stats, true);
+    }
+    return IVF_OK;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------- C ABI
@@ -1238,24 +1385,7 @@ ivf_status ivf_init_seeds(ivf_handle* h, const int32_t* seeds) {
 ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
     if (!h || !assign) return fail(h, IVF_ERR_ARG, "null argument");
     if (!h->has_means) return fail(h, IVF_ERR_STATE, "no means: call ivf_set_means or ivf_init_seeds");
-    const hipStream_t s = h->stream;
-    const Plan& p = h->plan;
-    if (stats) HIPCHK(h, hipEventRecord(h->ev[0], s));
-    HIPCHK(h, launch_clear_counters(h->cnt, s));
-    HIPCHK(h, hipMemcpyAsync(h->prev, assign, sizeof(int32_t) * (size_t)h->n,
-                             hipMemcpyDeviceToDevice, s));
-    const WalkArgs w = walk_args(h);
-    if (stats) HIPCHK(h, hipEventRecord(h->ev[4], s));
-    HIPCHK(h, launch_walk(w, h->opt.valtype, p.waves, p.lds_bytes, h->walk_grid, s));
-    if (stats) HIPCHK(h, hipEventRecord(h->ev[5], s));
-    ivf_status st = assign_finish(h, assign);
-    if (st != IVF_OK) return st;
-    if (stats) {
-        HIPCHK(h, hipEventRecord(h->ev[1], s));
-        HIPCHK(h, hipStreamSynchronize(s));
-        return assign_stats(h, stats, true);
-    }
-    return IVF_OK;
+    return assign_with(h, assign, stats, handle_bufs(h));
 }
 
 ivf_status ivf_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats) {

@@ -1,4 +1,5 @@
-// Argument blocks and launch wrappers of the device kernels.
+// Argument blocks and launch wrappers of the assignment walk, its merge and
+// FP64 re-score, IVFD, and the inverted-file rebuild the walk reads.
 #pragma once
 
 #include "ivf_internal.h"
@@ -112,89 +113,7 @@ hipError_t launch_ivfd_overlap(const int64_t* x_ptr, const int32_t* x_idx, int64
 hipError_t launch_max_row_norm(const int64_t* ptr, const float* val32, const double* val64,
                                int64_t rows, unsigned long long* out, hipStream_t s);
 
-// ----------------------------------------------------------------- update side
-struct ObjectView {
-    const int64_t* x_ptr;
-    const int32_t* x_idx;
-    const float* x_val;
-    int64_t n, d, nnz;
-};
-
-// Validation of the object set: raises bits of Counters::error_flags.
-hipError_t launch_validate_objects(const ObjectView& x, Counters* cnt, hipStream_t s);
-// Validation of caller-given mean-major means.
-hipError_t launch_validate_means(const int64_t* ptr, const int32_t* idx, const double* val,
-                                 int32_t k, int64_t d, int64_t nnz, Counters* cnt,
-                                 hipStream_t s);
-// rowid[e] = object of entry e.
-hipError_t launch_row_ids(const int64_t* ptr, int64_t n, int32_t* rowid, hipStream_t s);
-hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s);
-hipError_t launch_copy_keys(const int32_t* in, uint32_t* out, int64_t n, hipStream_t s);
-// After sorting (term, position): term-major view of the objects, the object
-// of every entry and its (term, FP32 value bits).
-hipError_t launch_build_xt(const uint32_t* sorted_terms, const uint32_t* sorted_pos,
-                           const int32_t* rowid, const float* x_val, int64_t nnz,
-                           int32_t* xt_obj, uint2* xt_tv, hipStream_t s);
-// Per-term fixed-point scale: every member sum of term t is exact in units of
-// 2^shift[t] unless the term's values span too wide a range (then rounded).
-hipError_t launch_term_shift(const int32_t* x_idx, const float* x_val, int64_t nnz, int64_t d,
-                             int32_t* emin, int32_t* emax, int32_t* count, int16_t* shift,
-                             Counters* cnt, hipStream_t s);
-
-// Segments per work item of the update's norm pass, and the most items any
-// update of k clusters over nnz object entries can have.
-constexpr int64_t kNormChunk = 4096;
-inline int64_t norm_item_bound(int64_t k, int64_t nnz) { return k + nnz / kNormChunk + 1; }
-
-struct UpdateArgs {
-    int64_t n, d, nnz;
-    int32_t k;
-    const int32_t* assign;
-    const int32_t* xt_obj;
-    const uint2* xt_tv;     // (term, FP32 value bits) per term-major entry
-    const int16_t* shift;
-    // sort buffers (nnz)
-    uint32_t* keys;
-    uint32_t* keys_alt;
-    uint2* pay;             // (term, value) of the entries in cluster order
-    // segments (nnz capacity)
-    uint32_t* flag;
-    uint32_t* segpos;
-    unsigned long long* seg_acc;
-    int32_t* seg_j;
-    int32_t* seg_t;
-    // clusters
-    int64_t* size;      // [k]
-    int64_t* cstart;    // [k + 1]
-    double* nrm;        // [k]
-    double* objpart;    // [k]
-    int64_t* newcnt;    // [k]
-    int64_t* scal;      // device scalars: [0] valid entries, [1] segments
-    int64_t* norm_items;  // [k + 1] norm work items per cluster, then their offsets
-    double* norm_part;    // [2 * norm_item_bound(k, nnz)] per item: sum w^2, mu(old) . s
-    // old means (mean-major) and new means
-    const int64_t* old_ptr;
-    const int32_t* old_idx;
-    const double* old_val;
-    int64_t* new_ptr;
-    int64_t new_cap;    // entries the new-means buffers hold
-    int32_t* new_idx;
-    double* new_val;
-    int32_t* new_row;
-    Counters* cnt;
-    void* tmp;
-};
-
-// Update, first half: group entries by cluster, exact per-(cluster, term)
-// sums, sizes, norms, exact objective, new row counts and row pointers.
-hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s);
-// Update, second half: write the new mean-major means (after capacity check).
-hipError_t launch_update_fill(UpdateArgs& a, hipStream_t s);
-hipError_t launch_objective_exact(const double* objpart, int32_t k, double* out,
-                                  hipStream_t s);
-// Row ids of mean-major means (for caller-given means).
-hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStream_t s);
-
+// ------------------------------------------------ inverted-file rebuild
 struct IvfArgs {
     int64_t d, nnzM;          // nnzM: entries, or their capacity if nnz_dev is set
     const int64_t* nnz_dev;   // device-side entry count (nullable)
@@ -224,7 +143,5 @@ hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s);
 // Phase 2: dense slabs filled (the array holds slab_cap elements; slices that
 // do not fit stay sparse), descriptors of dense slices pointed at them.
 hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_cap, hipStream_t s);
-hipError_t launch_seed_assign(const int32_t* seeds, int32_t k, int64_t n, int32_t* assign,
-                              hipStream_t s);
 
 }  // namespace ivf

@@ -10,12 +10,9 @@
 // count: a deterministic segmented reduction).  The mean is then the sum
 // divided by |C_j| and by the FP64 2-norm, as the paper orders the update.
 // Clusters without members keep their previous mean.
-//
-// The inverted-file rebuild stably sorts the new mean-major entries by term,
-// so every term's list comes out in ascending cluster order, the order the
-// paper's update loop produces.
 #include "ivf_internal.h"
 #include "kernels.h"
+#include "update.h"
 
 namespace ivf {
 namespace {
@@ -209,8 +206,11 @@ __global__ void k_zero_i64(int64_t* p, int64_t n) {
 
 // Entries sorted by cluster carry their (term, value) payload, so runs of
 // equal (cluster, term) are found by reading neighbours, not by gathers.
+// tmask: the bits of the payload's first word that hold the term (the others
+// mark a delta entry that subtracts its value, see k_delta_emit).
 __global__ void k_seg_flags(const uint32_t* __restrict__ keys, const uint2* __restrict__ pay,
-                            int64_t nnz, int32_t k, uint32_t* __restrict__ flag, int64_t* scal) {
+                            int64_t nnz, int32_t k, uint32_t tmask, uint32_t* __restrict__ flag,
+                            int64_t* scal) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
          q += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t key = keys[q];
@@ -220,7 +220,7 @@ __global__ void k_seg_flags(const uint32_t* __restrict__ keys, const uint2* __re
             if (q == 0) f = 1;
             else {
                 const uint32_t kp = keys[q - 1];
-                f = (kp != key || pay[q].x != pay[q - 1].x) ? 1u : 0u;
+                f = (kp != key || ((pay[q].x ^ pay[q - 1].x) & tmask) != 0u) ? 1u : 0u;
             }
             if (q == nnz - 1 || keys[q + 1] >= (uint32_t)k) scal[0] = q + 1;
         }
@@ -274,8 +274,11 @@ __device__ inline int64_t readlane_i64(int64_t x, int l) {
 // accumulator.  A run reaching the chunk's last lane is carried into the next
 // chunk, so a long segment costs one atomic per wave, not one per lane.  The
 // sums are integers: exact and independent of the order of the additions.
+// Entries whose payload carries bits outside tmask subtract their value (two's
+// complement: the sums are exact modulo 2^64, and every final sum is in range).
 __global__ __launch_bounds__(kThreads) void k_seg_sums(const uint32_t* __restrict__ keys,
                                                        const uint2* __restrict__ pay,
+                                                       uint32_t tmask,
                                                        const uint32_t* __restrict__ flag,
                                                        const uint32_t* __restrict__ segpos,
                                                        const int16_t* __restrict__ shift,
@@ -297,13 +300,14 @@ __global__ __launch_bounds__(kThreads) void k_seg_sums(const uint32_t* __restric
         unsigned long long v = 0;
         if (valid) {
             const uint2 tv = pay[q];
-            const int32_t t = (int32_t)tv.x;
+            const int32_t t = (int32_t)(tv.x & tmask);
             sg = (int64_t)segpos[q] + flag[q] - 1;
             if (flag[q]) {
                 seg_j[sg] = (int32_t)keys[q];
                 seg_t[sg] = t;
             }
             v = to_fixed(__uint_as_float(tv.y), shift[t]);
+            if (tv.x & ~tmask) v = 0ull - v;
         }
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
@@ -478,115 +482,174 @@ __global__ void k_mean_rows(const int64_t* ptr, int32_t k, int32_t* row) {
     for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) row[e] = (int32_t)j;
 }
 
-// ----------------------------------------------------------- inverted file
-__device__ inline uint32_t bf16_rne(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
+// ------------------------------------------------------ incremental update
+// The member sums of every (cluster, term) are exact integers, so the sums of
+// a new assignment are the stored sums of the previous one, minus the values
+// of the objects that left each cluster, plus those of the objects that
+// joined it: bit for bit what the full segmented reduction gives.  The stored
+// table lists (cluster, term, sum) for every nonzero sum in (cluster, term)
+// order.
 
-__global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __restrict__ mm_row,
-                           const double* __restrict__ mm_val, int64_t nnzM, const int64_t* n_dev,
-                           int32_t k_r, int valtype, int32_t* __restrict__ cid,
-                           void* __restrict__ post) {
-    nnzM = bounded_count(nnzM, n_dev);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t p = vals[q];
-        const int32_t j = mm_row[p];
-        const double u = mm_val[p];
-        cid[q] = j;
-        const float f = (float)u;
-        if (valtype == IVF_VAL_F32) {
-            reinterpret_cast<uint2*>(post)[q] = make_uint2((uint32_t)j, __float_as_uint(f));
-        } else {
-            const uint32_t local = (uint32_t)(j % k_r);
-            uint32_t h;
-            if (valtype == IVF_VAL_BF16) h = bf16_rne(f);
-            else h = (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)f);
-            reinterpret_cast<uint32_t*>(post)[q] = local | (h << 16);
+__device__ inline int32_t valid_cluster(int32_t a, int32_t k) { return (a >= 0 && a < k) ? a : -1; }
+
+// Delta entries of object i: its row once for the cluster it left and once
+// for the cluster it joined (0 if unchanged).  cnt[n] = 0 for the scan.
+__global__ void k_delta_count(const int64_t* __restrict__ x_ptr, int64_t n,
+                              const int32_t* __restrict__ assign,
+                              const int32_t* __restrict__ old_assign, int32_t k,
+                              int64_t* __restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t c = 0;
+        if (i < n) {
+            const int32_t a = valid_cluster(assign[i], k), o = valid_cluster(old_assign[i], k);
+            if (a != o) c = (x_ptr[i + 1] - x_ptr[i]) * ((a >= 0) + (o >= 0));
         }
+        cnt[i] = c;
     }
 }
 
-__global__ void k_ivf_ptr(const uint32_t* skeys, int64_t nnzM, const int64_t* n_dev, int64_t d,
-                          int64_t* ptr) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > d) return;
-    nnzM = bounded_count(nnzM, n_dev);
-    int64_t lo = 0, hi = nnzM;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (skeys[mid] < (uint32_t)t) lo = mid + 1; else hi = mid;
-    }
-    ptr[t] = lo;
-}
-
-// Per (term, range) slice: sparse start and count; dense slab size when the
-// slice holds at least `theta` of the range's clusters.
-__global__ void k_desc(const int64_t* ptr, const int32_t* cid, int64_t d, int32_t k, int32_t R,
-                       int32_t k_r, float theta, int32_t align, SliceDesc* desc, int64_t* dsz) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= d) {
-        if (t == d) dsz[d * R] = 0;
-        return;
-    }
-    const int64_t a = ptr[t], b = ptr[t + 1];
-    int64_t lo = a;
-    for (int32_t r = 0; r < R; ++r) {
-        const int64_t hi = lower_bound_i32(cid, lo, b, (r + 1) * k_r);
-        const int64_t cnt = hi - lo;
-        const int32_t kr = min(k_r, k - r * k_r);
-        SliceDesc ds;
-        ds.pos = lo;
-        ds.count = cnt;
-        desc[t * R + r] = ds;
-        // a dense slab's size is rounded up to whole 128-byte lines, so every
-        // slab starts on a line (0.5-0.8 % faster walks at 8M documents)
-        dsz[t * R + r] = (cnt > 0 && (float)cnt >= theta * (float)kr)
-                             ? (int64_t)((kr + align - 1) / align * align)
-                             : 0;
-        lo = hi;
-    }
-}
-
-__global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, int64_t nslices,
-                             int64_t cap) {
-    // a slice is dense iff its scanned offset grows: doff[s + 1] > doff[s];
-    // one that would not fit the slab capacity stays sparse (same scores)
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslices;
-         s += (int64_t)gridDim.x * blockDim.x)
-        if (doff[s + 1] > doff[s] && doff[s + 1] <= cap) desc[s].pos = -(doff[s] + 1);
-}
-
-template <typename T>
-__global__ void k_zero_t(T* p, int64_t n, const int64_t* n_dev = nullptr) {
-    if (n_dev) n = min(n, *n_dev);
+// The delta entries of the changed objects at their scanned offsets, keyed by
+// term: payload (cluster | 2^31 if the entry subtracts, FP32 value bits).
+__global__ void k_delta_emit(const int64_t* __restrict__ x_ptr, const int32_t* __restrict__ x_idx,
+                             const float* __restrict__ x_val, int64_t n,
+                             const int32_t* __restrict__ assign,
+                             const int32_t* __restrict__ old_assign, int32_t k,
+                             const int64_t* __restrict__ off, uint32_t* __restrict__ keys,
+                             uint2* __restrict__ pay) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (T)0;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (off[i + 1] == off[i]) continue;
+        const int32_t a = valid_cluster(assign[i], k), o = valid_cluster(old_assign[i], k);
+        const int64_t hb = x_ptr[i], he = x_ptr[i + 1];
+        int64_t q = off[i];
+        if (o >= 0)
+            for (int64_t e = hb; e < he; ++e, ++q) {
+                keys[q] = (uint32_t)x_idx[e];
+                pay[q] = make_uint2((uint32_t)o | 0x80000000u, __float_as_uint(x_val[e]));
+            }
+        if (a >= 0)
+            for (int64_t e = hb; e < he; ++e, ++q) {
+                keys[q] = (uint32_t)x_idx[e];
+                pay[q] = make_uint2((uint32_t)a, __float_as_uint(x_val[e]));
+            }
+    }
 }
 
-// Dense slabs take every entry of their slice at its cluster's offset.
-__global__ void k_slab_scatter(const uint32_t* __restrict__ skeys, const int32_t* __restrict__ cid,
-                               const void* __restrict__ post, const SliceDesc* __restrict__ desc,
-                               int64_t nnzM, const int64_t* n_dev, int64_t d, int32_t k,
-                               int32_t R, int32_t k_r, int valtype, void* __restrict__ slab) {
-    nnzM = bounded_count(nnzM, n_dev);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
+// Sorted by term, the entries are keyed again by cluster (the payload then
+// carries the term and the sign bit); a stable sort by cluster follows.
+__global__ void k_delta_rekey(uint32_t* __restrict__ keys, uint2* __restrict__ pay, int64_t m) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < m;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t t = skeys[q];
-        const int32_t j = cid[q];
-        if (t >= d || j < 0 || j >= k) continue;   // never true for validated means
-        const int32_t r = j / k_r;
-        const int64_t pos = desc[t * R + r].pos;
-        if (pos >= 0) continue;
-        const int64_t at = (-pos - 1) + (j - r * k_r);
-        if (valtype == IVF_VAL_F32)
-            reinterpret_cast<float*>(slab)[at] =
-                __uint_as_float(reinterpret_cast<const uint2*>(post)[q].y);
-        else
-            reinterpret_cast<uint16_t*>(slab)[at] =
-                (uint16_t)(reinterpret_cast<const uint32_t*>(post)[q] >> 16);
+        const uint32_t t = keys[q];
+        const uint2 p = pay[q];
+        keys[q] = p.x & 0x7fffffffu;
+        pay[q] = make_uint2(t | (p.x & 0x80000000u), p.y);
+    }
+}
+
+// Each delta segment (cluster j, term t, signed sum) added into the table if
+// (j, t) is there (cstart: the table's cluster starts); otherwise it is an
+// insertion before table position lb (its sum is then a positive total of
+// joined values), counted in add[lb].  ins[d] = 1 marks an insertion; it is
+// cleared up to `cap` (>= the segment count), the length the host scans.
+__global__ void k_delta_apply(const int32_t* __restrict__ dj, const int32_t* __restrict__ dt,
+                              const unsigned long long* __restrict__ dacc,
+                              const int64_t* __restrict__ scal, int64_t cap,
+                              const int64_t* __restrict__ cstart,
+                              const int32_t* __restrict__ tab_t,
+                              unsigned long long* __restrict__ tab_acc,
+                              uint32_t* __restrict__ ins, uint32_t* __restrict__ ins_lb,
+                              uint32_t* __restrict__ add) {
+    const int64_t nd = scal[1];
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < cap;
+         d += (int64_t)gridDim.x * blockDim.x) {
+        if (d >= nd) {
+            ins[d] = 0;
+            continue;
+        }
+        const int32_t j = dj[d], t = dt[d];
+        const int64_t e = cstart[j + 1];
+        int64_t lo = cstart[j], hi = e;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (tab_t[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        const unsigned long long v = dacc[d];
+        uint32_t f = 0;
+        if (lo < e && tab_t[lo] == t) {
+            tab_acc[lo] += v;   // one delta segment per (j, t): no other writer
+        } else if (v != 0ull) {
+            f = 1;
+            ins_lb[d] = (uint32_t)lo;
+            atomicAdd(&add[lo], 1u);
+        }
+        ins[d] = f;
+    }
+}
+
+// Per table position p (and p = m for insertions after the last entry): the
+// entry survives if its sum is nonzero (high word) and add[p] insertions go
+// before it (low word); one scan of the packed counts gives both prefixes.
+__global__ void k_merge_counts(const unsigned long long* __restrict__ tab_acc, int64_t m,
+                               const uint32_t* __restrict__ add, int64_t* __restrict__ c) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= m;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t keep = (p < m && tab_acc[p] != 0ull) ? 1 : 0;
+        c[p] = (keep << 32) | (int64_t)add[p];
+    }
+}
+
+// The new table: surviving entries after the insertions that precede them,
+// insertions at the surviving entries before their position plus their rank
+// among all insertions.  The new entry count goes to scal[1].
+__global__ void k_merge_scatter(const int32_t* __restrict__ tab_j, const int32_t* __restrict__ tab_t,
+                                const unsigned long long* __restrict__ tab_acc, int64_t m,
+                                const uint32_t* __restrict__ add, const int64_t* __restrict__ cs,
+                                const int32_t* __restrict__ dj, const int32_t* __restrict__ dt,
+                                const unsigned long long* __restrict__ dacc,
+                                const uint32_t* __restrict__ ins, const uint32_t* __restrict__ ins_lb,
+                                const uint32_t* __restrict__ ipos, int64_t* __restrict__ scal,
+                                int32_t* __restrict__ nj, int32_t* __restrict__ nt,
+                                unsigned long long* __restrict__ nacc) {
+    const int64_t nd = scal[1];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t p = g; p < m; p += stride) {
+        const unsigned long long v = tab_acc[p];
+        if (v == 0ull) continue;
+        const int64_t at = (cs[p] >> 32) + (cs[p] & 0xffffffffll) + add[p];
+        nj[at] = tab_j[p];
+        nt[at] = tab_t[p];
+        nacc[at] = v;
+    }
+    for (int64_t d = g; d < nd; d += stride) {
+        if (!ins[d]) continue;
+        const int64_t at = (cs[ins_lb[d]] >> 32) + ipos[d];
+        nj[at] = dj[d];
+        nt[at] = dt[d];
+        nacc[at] = dacc[d];
+    }
+}
+
+__global__ void k_merge_total(const int64_t* __restrict__ cs, const uint32_t* __restrict__ add,
+                              int64_t m, int64_t* __restrict__ scal) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        scal[1] = (cs[m] >> 32) + (cs[m] & 0xffffffffll) + add[m];
+}
+
+// The full reduction's segments become the stored table (count at scal[1]).
+__global__ void k_copy_table(const int32_t* __restrict__ sj, const int32_t* __restrict__ st,
+                             const unsigned long long* __restrict__ sacc,
+                             const int64_t* __restrict__ scal, int64_t cap,
+                             int32_t* __restrict__ tj, int32_t* __restrict__ tt,
+                             unsigned long long* __restrict__ tacc) {
+    const int64_t m = min(scal[1], cap);
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        tj[p] = sj[p];
+        tt[p] = st[p];
+        tacc[p] = sacc[p];
     }
 }
 
@@ -665,12 +728,24 @@ hipError_t launch_term_shift(const int32_t* x_idx, const float* x_val, int64_t n
     return hipGetLastError();
 }
 
+namespace {
+hipError_t launch_sizes(const int32_t* assign, int64_t n, int32_t k, int64_t* size, int64_t* scal,
+                        hipStream_t s) {
+    k_zero_i64<<<capped(k + 1), kThreads, 0, s>>>(size, k);
+    k_zero_i64<<<1, kThreads, 0, s>>>(scal, 4);
+    k_sizes<<<capped(n), kThreads, 0, s>>>(assign, n, k, size);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s) {
+    HIP_RET(launch_update_segments(a, s));
+    return launch_update_norms(a, s);
+}
+
+hipError_t launch_update_segments(UpdateArgs& a, hipStream_t s) {
     const int64_t nnz = a.nnz;
-    k_zero_i64<<<capped(a.k + 1), kThreads, 0, s>>>(a.size, a.k);
-    k_zero_i64<<<1, kThreads, 0, s>>>(a.scal, 4);
-    k_sizes<<<capped(a.n), kThreads, 0, s>>>(a.assign, a.n, a.k, a.size);
-    HIP_RET(hipGetLastError());
+    HIP_RET(launch_sizes(a.assign, a.n, a.k, a.size, a.scal, s));
     if (nnz > 0) {
         k_keys<<<capped(nnz), kThreads, 0, s>>>(a.xt_obj, a.assign, nnz, a.k, a.keys);
         HIP_RET(hipGetLastError());
@@ -680,16 +755,21 @@ hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s) {
         HIP_RET(radix_sort_pairs_u64(a.keys, a.pay, a.keys_alt,
                                      reinterpret_cast<uint2*>(a.seg_acc), nnz, bits_for(a.k),
                                      a.tmp, s, a.xt_tv));
-        k_seg_flags<<<capped(nnz), kThreads, 0, s>>>(a.keys, a.pay, nnz, a.k, a.flag, a.scal);
+        k_seg_flags<<<capped(nnz), kThreads, 0, s>>>(a.keys, a.pay, nnz, a.k, 0xffffffffu, a.flag,
+                                                     a.scal);
         HIP_RET(hipGetLastError());
         HIP_RET(exclusive_scan_u32(a.flag, a.segpos, nnz, a.tmp, s));
         k_seg_count<<<1, 64, 0, s>>>(a.flag, a.segpos, nnz, a.scal);
         k_zero_segs<<<capped(nnz), kThreads, 0, s>>>(a.seg_acc, a.scal, nnz);
-        k_seg_sums<<<grid_for(nnz, kRun), kThreads, 0, s>>>(a.keys, a.pay, a.flag, a.segpos,
-                                                            a.shift, a.scal, a.seg_acc, a.seg_j,
-                                                            a.seg_t);
+        k_seg_sums<<<grid_for(nnz, kRun), kThreads, 0, s>>>(a.keys, a.pay, 0xffffffffu, a.flag,
+                                                            a.segpos, a.shift, a.scal, a.seg_acc,
+                                                            a.seg_j, a.seg_t);
         HIP_RET(hipGetLastError());
     }
+    return hipSuccess;
+}
+
+hipError_t launch_update_norms(UpdateArgs& a, hipStream_t s) {
     k_cstart<<<grid_for(a.k + 1), kThreads, 0, s>>>(a.seg_j, a.scal, a.k, a.cstart);
     k_norm_items<<<grid_for(a.k + 1), kThreads, 0, s>>>(a.size, a.cstart, a.k, a.norm_items);
     HIP_RET(hipGetLastError());
@@ -701,6 +781,65 @@ hipError_t launch_update_sums(UpdateArgs& a, hipStream_t s) {
     // new row pointers: exclusive scan of k + 1 counts (the last is 0)
     k_zero_i64<<<1, 64, 0, s>>>(a.newcnt + a.k, 1);
     HIP_RET(exclusive_scan_i64(a.newcnt, a.new_ptr, (int64_t)a.k + 1, a.tmp, s));
+    return hipGetLastError();
+}
+
+hipError_t launch_delta_count(const int64_t* x_ptr, int64_t n, const int32_t* assign,
+                              const int32_t* old_assign, int32_t k, int64_t* off, void* tmp,
+                              hipStream_t s) {
+    k_delta_count<<<capped(n + 1), kThreads, 0, s>>>(x_ptr, n, assign, old_assign, k, off);
+    HIP_RET(hipGetLastError());
+    return exclusive_scan_i64(off, off, n + 1, tmp, s);
+}
+
+hipError_t launch_delta_update(DeltaArgs& a, hipStream_t s) {
+    HIP_RET(launch_sizes(a.assign, a.n, a.k, a.size, a.scal, s));
+    const int64_t m = a.entries;
+    if (m > 0) {
+        k_delta_emit<<<capped(a.n), kThreads, 0, s>>>(a.x_ptr, a.x_idx, a.x_val, a.n, a.assign,
+                                                      a.old_assign, a.k, a.off, a.keys, a.pay);
+        HIP_RET(hipGetLastError());
+        // (cluster, term) order: stable by term, then stable by cluster
+        HIP_RET(radix_sort_pairs_u64(a.keys, a.pay, a.keys_alt, a.pay_alt, m,
+                                     bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, nullptr));
+        k_delta_rekey<<<capped(m), kThreads, 0, s>>>(a.keys, a.pay, m);
+        HIP_RET(hipGetLastError());
+        HIP_RET(radix_sort_pairs_u64(a.keys, a.pay, a.keys_alt, a.pay_alt, m, bits_for(a.k),
+                                     a.tmp, s, nullptr));
+        k_seg_flags<<<capped(m), kThreads, 0, s>>>(a.keys, a.pay, m, a.k, 0x7fffffffu, a.flag,
+                                                   a.scal);
+        HIP_RET(hipGetLastError());
+        HIP_RET(exclusive_scan_u32(a.flag, a.segpos, m, a.tmp, s));
+        k_seg_count<<<1, 64, 0, s>>>(a.flag, a.segpos, m, a.scal);
+        k_zero_segs<<<capped(m), kThreads, 0, s>>>(a.dacc, a.scal, m);
+        k_seg_sums<<<grid_for(m, kRun), kThreads, 0, s>>>(a.keys, a.pay, 0x7fffffffu, a.flag,
+                                                          a.segpos, a.shift, a.scal, a.dacc,
+                                                          a.dj, a.dt);
+        HIP_RET(hipGetLastError());
+    }
+    // merge the delta segments (count at scal[1]) into the table
+    const int64_t tn = a.tab_n;
+    k_fill_i32<<<capped(tn + 1), kThreads, 0, s>>>(reinterpret_cast<int32_t*>(a.add), tn + 1, 0);
+    if (m > 0) {
+        k_delta_apply<<<capped(m), kThreads, 0, s>>>(a.dj, a.dt, a.dacc, a.scal, m, a.cstart,
+                                                     a.tab_t, a.tab_acc, a.ins, a.ins_lb, a.add);
+        HIP_RET(hipGetLastError());
+        HIP_RET(exclusive_scan_u32(a.ins, a.ipos, m, a.tmp, s));
+    }
+    k_merge_counts<<<capped(tn + 1), kThreads, 0, s>>>(a.tab_acc, tn, a.add, a.cs);
+    HIP_RET(hipGetLastError());
+    HIP_RET(exclusive_scan_i64(a.cs, a.cs, tn + 1, a.tmp, s));
+    k_merge_scatter<<<capped(std::max<int64_t>(tn, m)), kThreads, 0, s>>>(
+        a.tab_j, a.tab_t, a.tab_acc, tn, a.add, a.cs, a.dj, a.dt, a.dacc, a.ins, a.ins_lb, a.ipos,
+        a.scal, a.new_j, a.new_t, a.new_acc);
+    k_merge_total<<<1, 64, 0, s>>>(a.cs, a.add, tn, a.scal);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_table(const int32_t* sj, const int32_t* st, const unsigned long long* sacc,
+                             const int64_t* scal, int64_t cap, int32_t* tj, int32_t* tt,
+                             unsigned long long* tacc, hipStream_t s) {
+    k_copy_table<<<capped(cap), kThreads, 0, s>>>(sj, st, sacc, scal, cap, tj, tt, tacc);
     return hipGetLastError();
 }
 
@@ -717,46 +856,6 @@ hipError_t launch_objective_exact(const double* objpart, int32_t k, double* out,
 
 hipError_t launch_mean_rows(const int64_t* ptr, int32_t k, int32_t* row, hipStream_t s) {
     k_mean_rows<<<grid_for(k), kThreads, 0, s>>>(ptr, k, row);
-    return hipGetLastError();
-}
-
-hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
-    // a.nnzM: the entry count, or the capacity when a.nnz_dev holds the count
-    if (a.nnzM > 0) {
-        k_copy_keys<<<capped(a.nnzM), kThreads, 0, s>>>(a.mm_idx, a.keys, a.nnzM, a.nnz_dev);
-        HIP_RET(hipGetLastError());
-        HIP_RET(radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.nnzM,
-                                 bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, a.iota,
-                                 a.nnz_dev));
-        k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM,
-                                                       a.nnz_dev, a.k_r, a.valtype, a.cid,
-                                                       a.post);
-        HIP_RET(hipGetLastError());
-    }
-    k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.nnz_dev, a.d, a.ivf_ptr);
-    k_desc<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.ivf_ptr, a.cid, a.d, a.k, a.R, a.k_r,
-                                                  a.dense_threshold,
-                                                  a.valtype == IVF_VAL_F32 ? 32 : 64, a.desc, a.dsz);
-    HIP_RET(hipGetLastError());
-    return exclusive_scan_i64(a.dsz, a.dsz, a.d * a.R + 1, a.tmp, s);
-}
-
-hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_cap, hipStream_t s) {
-    // slab_cap: elements the slab array holds; the needed total is at dsz[d * R]
-    const int64_t ns = a.d * a.R;
-    if (slab_cap <= 0) return hipSuccess;
-    k_desc_dense<<<capped(ns), kThreads, 0, s>>>(a.desc, a.dsz, ns, slab_cap);
-    const int64_t* total = a.dsz + ns;
-    if (a.valtype == IVF_VAL_F32)
-        k_zero_t<float><<<capped(slab_cap), kThreads, 0, s>>>(reinterpret_cast<float*>(a.slab),
-                                                               slab_cap, total);
-    else
-        k_zero_t<uint16_t><<<capped(slab_cap), kThreads, 0, s>>>(
-            reinterpret_cast<uint16_t*>(a.slab), slab_cap, total);
-    if (a.nnzM > 0)
-        k_slab_scatter<<<capped(a.nnzM), kThreads, 0, s>>>(a.keys, a.cid, a.post, a.desc, a.nnzM,
-                                                           a.nnz_dev, a.d, a.k, a.R, a.k_r,
-                                                           a.valtype, a.slab);
     return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ def test_algorithmic_bytes_and_the_stale_counter_rule(tmp_path, monkeypatch):
             == bench.walk_bytes(10, 3, 2, 1, "f32") + 16 + 48 + 5 * 32)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     os.makedirs(tmp_path / "profiles")
-    monkeypatch.setattr(bench, "kernel_hash", lambda sources=("assign.hip", "update.hip"): "abc")
+    monkeypatch.setattr(bench, "kernel_hash", lambda sources=("assign.hip", "invfile.hip"): "abc")
     p = tmp_path / "profiles" / "walk_w_f32_levels.json"
     p.write_text(json.dumps({"kernel_hash": "abc", "l2_read_bytes": 123.0}))
     assert bench.level_counters("k_walk", "w", "f32")["l2_read_bytes"] == 123.0
@@ -116,7 +116,7 @@ def test_level_summary_scales_requests_by_the_probes(tmp_path, monkeypatch):
     did = 0
     # probes: (warm, timed) per level; 128-byte L1->L2 requests, 64-byte fabric ones
     for level in bench.CEILINGS:
-        for _ in range(2):
+        for _ in range(2 * len(bench.PROBE_SHAPES)):
             nb = bench.probe_bytes(level, cus)
             for name, v in (("TCP_TCC_READ_REQ_sum", nb / 128), ("TCC_EA0_RDREQ_sum", nb / 64),
                             ("TCC_HIT_sum", 1.0), ("TCC_MISS_sum", 1.0)):

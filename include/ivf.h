@@ -177,6 +177,24 @@ ivf_status ivf_init_seeds(ivf_handle* h, const int32_t* seeds);
 ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats);
 
 /*
+ * ivf_assign_static: ivf_assign for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The same step with the same results, bit for bit; its
+ * per-call scratch (the previous assignment, the FP64 re-score queue and the
+ * walk's per-(object, cluster range) records: n * (16 * ranges + 8) bytes,
+ * each part rounded up to 256 bytes) lives in a fixed 64 MiB array the library
+ * holds on every GPU it runs on until the process ends, instead of in the
+ * handle's buffers.  Calls no allocating routine.
+ *   h, assign, stats  as for ivf_assign; the handle's device must be current.
+ * Errors: as ivf_assign; IVF_ERR_CAPACITY (nothing launched) when the step
+ * needs more than the 64 MiB; IVF_ERR_STATE when another device is current.
+ * Every call on one GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap on one GPU (any handles, any streams, without stats so
+ * that they do not synchronise) race; order them, e.g. on one stream.
+ */
+ivf_status ivf_assign_static(ivf_handle* h, int32_t* assign, ivf_stats* stats);
+
+/*
  * ivf_update: one update step (Alg. 3, update part) from the assignment
  * (device int32 [n], -1 entries ignored): exact member sums, FP64 norms and
  * renormalisation, clusters without members keep their mean, then the

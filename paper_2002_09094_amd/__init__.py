@@ -186,6 +186,17 @@ class IVFKMeans:
               self._h)
         return st.to_dict() if stats else None
 
+    def assign_static(self, assign, stats=True):
+        """``assign`` with its per-call scratch in the library's fixed per-device
+        array (no device allocation); the same results bit for bit.  Calls on one
+        GPU must not overlap."""
+        import torch
+        _need_cuda(assign, torch.int32, "assign")
+        st = _lib.ivf_stats() if stats else None
+        check(_lib.get().ivf_assign_static(self._h, _ptr(assign),
+                                           ctypes.byref(st) if stats else None), self._h)
+        return st.to_dict() if stats else None
+
     def assign_ivfd(self, assign, objects_per_range=0, stats=True):
         """The assignment step of IVFD (the objects inverted, each mean a
         query): the same partition as ``assign``; FP32 handles only."""

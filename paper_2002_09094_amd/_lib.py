@@ -59,6 +59,7 @@ SIGNATURES = {
     "ivf_set_means": (c_int32, [c_void_p, ctypes.POINTER(ivf_means)]),
     "ivf_init_seeds": (c_int32, [c_void_p, c_void_p]),
     "ivf_assign": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ivf_stats)]),
+    "ivf_assign_static": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_update": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_iterate": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(ivf_stats)]),
     "ivf_converge": (c_int32, [c_void_p, c_int32, c_void_p, ctypes.POINTER(ivf_stats),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -566,7 +567,7 @@ WalkArgs walk_args(ivf_handle* h) {
 
 // Per-call scratch of an assignment step: the previous assignment, the walk's
 // range records [n * R] and the FP64 re-score queue [n].  The handle's own
-// buffers, or another fixed set of the same sizes.
+// buffers, or (ivf_assign_static) the library's fixed per-device array.
 struct AssignBufs {
     int32_t* prev;
     RangeRec* rec;
@@ -971,6 +972,15 @@ struct ivf_batch {
     std::string err;
 };
 
+// ------------------------------------------------ allocation-free assignment
+// One fixed array per GPU for ivf_assign_static: the per-call scratch of an
+// assignment step (previous assignment, FP64 re-score queue, range records),
+// each part starting on a 256-byte boundary.  In host code `scratch` names a
+// host-side stand-in; the device address comes from hipGetSymbolAddress, once
+// per device, and only that address is handed to kernels and copies.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 ivf_status bfail(ivf_batch* b, ivf_status st, const std::string& msg) {
@@ -1241,6 +1251,33 @@ ivf_status assign_with(ivf_handle* h, int32_t* assign, ivf_stats* stats, const A
     return IVF_OK;
 }
 
+// ------------------------------------------------ allocation-free assignment
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t static_scratch_need(const ivf_handle* h) {
+    const size_t n = (size_t)h->n;
+    return align256(n * sizeof(int32_t)) * 2 + n * (size_t)h->plan.R * sizeof(RangeRec);
+}
+
+// The device address of this device's array, looked up on the first call on it.
+ivf_status static_scratch(ivf_handle* h, int dev, unsigned char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(h, IVF_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                            hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return IVF_OK;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------- C ABI
@@ -1386,6 +1423,31 @@ ivf_status ivf_assign(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
     if (!h || !assign) return fail(h, IVF_ERR_ARG, "null argument");
     if (!h->has_means) return fail(h, IVF_ERR_STATE, "no means: call ivf_set_means or ivf_init_seeds");
     return assign_with(h, assign, stats, handle_bufs(h));
+}
+
+ivf_status ivf_assign_static(ivf_handle* h, int32_t* assign, ivf_stats* stats) {
+    if (!h || !assign) return fail(h, IVF_ERR_ARG, "null argument");
+    if (!h->has_means) return fail(h, IVF_ERR_STATE, "no means: call ivf_set_means or ivf_init_seeds");
+    const size_t need = static_scratch_need(h);
+    if (need > kStaticScratchBytes)
+        return fail(h, IVF_ERR_CAPACITY,
+                    "ivf_assign_static: the step needs " + std::to_string(need) +
+                        " bytes of scratch (n * (16 * ranges + 8), rounded), beyond the fixed " +
+                        std::to_string(kStaticScratchBytes) + " bytes; use ivf_assign");
+    int dev = -1;
+    HIPCHK(h, hipGetDevice(&dev));
+    if (dev != h->device)
+        return fail(h, IVF_ERR_STATE, "ivf_assign_static: the handle's device must be current");
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, IVF_ERR_CAPACITY, "device index too large");
+    unsigned char* base = nullptr;
+    ivf_status st = static_scratch(h, dev, &base);
+    if (st != IVF_OK) return st;
+    const size_t n4 = align256((size_t)h->n * sizeof(int32_t));
+    AssignBufs b{};
+    b.prev = reinterpret_cast<int32_t*>(base);
+    b.rescore_list = reinterpret_cast<int32_t*>(base + n4);
+    b.rec = reinterpret_cast<RangeRec*>(base + 2 * n4);
+    return assign_with(h, assign, stats, b);
 }
 
 ivf_status ivf_update(ivf_handle* h, const int32_t* assign, ivf_stats* stats) {

@@ -467,27 +467,33 @@ def summarize_levels(workload, valtype, out_json, out_txt, command, kernel, cus,
 
 def summarize_counters(fetch_csv, write_csv, workload, valtype, out_json, command,
                        kernel="k_walk"):
-    """HBM traffic of the last launch of `kernel` from FETCH_SIZE and
+    """Memory-side traffic of the last launch of `kernel` from FETCH_SIZE and
     WRITE_SIZE runs (KiB per dispatch), each scaled so that the calibration
-    copy of COPY_BYTES reads and writes exactly COPY_BYTES."""
+    copy of COPY_BYTES reads and writes exactly COPY_BYTES.  fetch_csv "-":
+    writes only."""
     def pick(path, counter):
         rows = [r for r in _csv_rows(path) if r["Counter_Name"] == counter]
         copies = [float(r["Counter_Value"]) for r in rows
                   if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1e5][:3]
         walks = [r for r in rows if "::%s<" % kernel in r["Kernel_Name"]]
         return copies, walks
-    fc, fw = pick(fetch_csv, "FETCH_SIZE")
     wc, ww = pick(write_csv, "WRITE_SIZE")
-    f_scale = COPY_BYTES / (1024.0 * sum(fc) / len(fc))
     w_scale = COPY_BYTES / (1024.0 * sum(wc) / len(wc))
-    fetch = float(fw[-1]["Counter_Value"]) * 1024.0 * f_scale
     write = float(ww[-1]["Counter_Value"]) * 1024.0 * w_scale
+    if fetch_csv == "-":   # the read side taken from request counters instead
+        fc, f_scale, fetch, fraw = None, None, None, None
+    else:
+        fc, fw = pick(fetch_csv, "FETCH_SIZE")
+        f_scale = COPY_BYTES / (1024.0 * sum(fc) / len(fc))
+        fraw = float(fw[-1]["Counter_Value"])
+        fetch = fraw * 1024.0 * f_scale
     out = {"kernel": kernel, "workload": workload, "valtype": valtype,
            "kernel_hash": kernel_hash(KERNEL_SOURCE[kernel]), "fetch_bytes": fetch,
            "write_bytes": write,
-           "hbm_bytes_per_launch": fetch + write, "fetch_scale": f_scale,
+           "hbm_bytes_per_launch": (fetch + write) if fetch is not None else None,
+           "fetch_scale": f_scale,
            "write_scale": w_scale, "copy_fetch_kib": fc, "copy_write_kib": wc,
-           "walk_fetch_kib_raw": float(fw[-1]["Counter_Value"]),
+           "walk_fetch_kib_raw": fraw,
            "walk_write_kib_raw": float(ww[-1]["Counter_Value"]), "command": command}
     with open(out_json, "w") as f:
         json.dump(out, f, indent=1)

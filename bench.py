@@ -116,7 +116,7 @@ def level_counters(kernel, workload, valtype):
     from the committed rocprofv3 counter summary, if it was taken on the
     current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "%s_%s_%s_levels.json"
-                        % (kernel.replace("k_", ""), workload, valtype))
+                        % (kernel[2:] if kernel.startswith("k_") else kernel, workload, valtype))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -130,7 +130,7 @@ def traffic_counters(kernel, workload, valtype):
     """Calibrated FETCH_SIZE / WRITE_SIZE bytes per launch of `kernel`, from the
     committed counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.json"
-                        % (kernel.replace("k_", ""), workload, valtype))
+                        % (kernel[2:] if kernel.startswith("k_") else kernel, workload, valtype))
     if not os.path.exists(path):
         return None
     with open(path) as f:

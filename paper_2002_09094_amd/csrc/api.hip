@@ -240,14 +240,18 @@ void free_handle(ivf_handle* h) {
         if (e) { (void)hipEventDestroy(e); e = nullptr; }
 }
 
+// Scratch for sorts of sort_need entries: the u32 sort buffers, and the
+// segment arrays (whose payload pair the inverted-file rebuild sorts with) for
+// max(object entries, sort_need).
 ivf_status ensure_scratch(ivf_handle* h, int64_t sort_need) {
     const int64_t scan = std::max<int64_t>((int64_t)h->k + 1, h->d * (int64_t)h->plan.R + 1);
+    const int64_t seg_need = std::max<int64_t>(h->nnz, sort_need);
     if (h->fixed) {
-        if (sort_need <= h->sc->sort_cap && h->nnz <= h->sc->seg_cap && scan <= h->sc->scan_need)
+        if (sort_need <= h->sc->sort_cap && seg_need <= h->sc->seg_cap && scan <= h->sc->scan_need)
             return IVF_OK;
         return fail(h, IVF_ERR_CAPACITY, "scratch exceeds the fixed capacity");
     }
-    HIPCHK(h, h->sc->ensure(sort_need, h->nnz, scan, h->stream));
+    HIPCHK(h, h->sc->ensure(sort_need, seg_need, scan, h->stream));
     return IVF_OK;
 }
 
@@ -304,11 +308,13 @@ ivf_status ensure_ivf(ivf_handle* h, int64_t need) {
 }
 
 ivf_status ensure_slab(ivf_handle* h, int64_t elems) {
+    // slices beyond the cap stay sparse (descriptors address slabs with 31 bits)
+    elems = std::min(elems, kMaxSlabElems);
     if (elems <= h->slab_cap || h->fixed) return IVF_OK;   // fixed: misfits stay sparse
     if (h->slab) (void)hipFree(h->slab);
     h->slab = nullptr;
     h->slab_cap = 0;
-    const int64_t cap = elems + elems / 4;
+    const int64_t cap = std::min(elems + elems / 4, kMaxSlabElems);
     HIPCHK(h, hipMalloc(&h->slab, (size_t)cap * (h->opt.valtype == IVF_VAL_F32 ? 4 : 2)));
     h->slab_cap = cap;
     return IVF_OK;
@@ -385,10 +391,9 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
     a.mm_val = h->mm_val[b];
     a.mm_row = h->mm_row[b];
     a.keys = h->sc->keys;
-    a.vals = h->sc->vals;
     a.keys_alt = h->sc->keys_alt;
-    a.vals_alt = h->sc->vals_alt;
-    a.iota = h->sc->iota;
+    a.pay = h->sc->pay;
+    a.pay_alt = reinterpret_cast<uint2*>(h->sc->seg_acc);
     a.ivf_ptr = h->ivf_ptr;
     a.desc = h->desc;
     a.dsz = h->dsz;
@@ -402,6 +407,9 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
 // Inverted file from mean-major buffer `b`.  With nnz_dev the entry count is
 // read on the device (capacity-bounded, no host synchronisation).
 ivf_status rebuild_ivf(ivf_handle* h, int b, int64_t nnzM, const int64_t* nnz_dev) {
+    if (nnzM >= ((int64_t)1 << 31) ||
+        (nnz_dev && std::max(h->mm_cap[0], h->mm_cap[1]) >= ((int64_t)1 << 31)))
+        return fail(h, IVF_ERR_CAPACITY, "the means hold 2^31 or more entries");
     ivf_status st = ensure_ivf(h, nnzM);
     if (st != IVF_OK) return st;
     IvfArgs a = ivf_args(h, b);

@@ -289,7 +289,7 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
     for (int64_t h0 = hb; h0 < he; h0 += kWave) {
         const int cnt = (int)min((int64_t)kWave, he - h0);
         float v = 0.f;
-        int64_t pos = 0, count = 0;
+        int32_t pos = 0, count = 0;
         if (lane < cnt) {
             const int32_t t = a.x_idx[h0 + lane];
             v = a.x_val[h0 + lane];
@@ -298,7 +298,7 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
             count = ds.count;
         }
         for (int hh = 0; hh < cnt; ++hh) {
-            const int64_t p = rl64(pos, hh), cn = rl64(count, hh);
+            const int64_t p = rl32(pos, hh), cn = rl32(count, hh);
             const float vv = rlf(v, hh);
             m += (int32_t)cn;
             if (p >= 0) {
@@ -310,9 +310,9 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
             if constexpr (VT != IVF_VAL_F32) {
                 // the next term's slice is dense too: both in one pass
                 if (hh + 1 < cnt && kr4 <= kDenseOne * kWave) {
-                    const int64_t p1 = rl64(pos, hh + 1);
+                    const int64_t p1 = rl32(pos, hh + 1);
                     if (p1 < 0) {
-                        m += (int32_t)rl64(count, hh + 1);
+                        m += (int32_t)rl32(count, hh + 1);
                         walk_dense2<VT>(slab_at<VT>(a, p), slab_at<VT>(a, p1), kr4, vv,
                                         rlf(v, hh + 1), tile, lane);
                         ++hh;
@@ -369,7 +369,7 @@ __device__ inline void walk_item(const WalkArgs& a, int64_t w, float* tile, int 
         rec.id = id >= 0 ? base + id : -1;
         rec.second = s2;
         rec.m = m;
-        a.rec[i * a.R + r] = rec;
+        a.rec[(int64_t)r * a.n + i] = rec;
     }
 }
 
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
         float b = 0.f, s2 = 0.f;
         int32_t id = -1;
         for (int r = 0; r < a.R; ++r) {
-            const RangeRec rec = a.rec[i * a.R + r];
+            const RangeRec rec = a.rec[(int64_t)r * a.n + i];
             m += rec.m;
             // ranges arrive in ascending cluster order: an equal best keeps the earlier
             if (rec.best > b) {
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
             const int32_t base = r * w.k_r;
             const int32_t kr = min(w.k_r, w.k - base);
             if (a.rec) {
-                const RangeRec rr = a.rec[i * w.R + r];
+                const RangeRec rr = a.rec[(int64_t)r * w.n + i];
                 if (cert_ub((double)rr.best, c, ab, g) < thr) continue;
                 if (rr.id >= 0 && cert_ub((double)rr.second, c, ab, g) < thr) {
                     const double e = exact_score(a, hb, he, rr.id, lane);

@@ -47,12 +47,18 @@ __device__ inline int64_t lower_bound_i32(const int32_t* a, int64_t lo, int64_t 
     return lo;
 }
 
-// Sort keys: the term of every mean entry (the first n_dev of n when given).
-__global__ void k_term_keys(const int32_t* in, uint32_t* out, int64_t n, const int64_t* n_dev) {
+// Sort keys and payload of every mean entry (the first n_dev of n when
+// given): its term, and its cluster with the FP32 rounding of its value.
+__global__ void k_term_entries(const int32_t* __restrict__ mm_idx,
+                               const int32_t* __restrict__ mm_row,
+                               const double* __restrict__ mm_val, int64_t n, const int64_t* n_dev,
+                               uint32_t* __restrict__ keys, uint2* __restrict__ pay) {
     n = bounded_count(n, n_dev);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (uint32_t)in[i];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        keys[e] = (uint32_t)mm_idx[e];
+        pay[e] = make_uint2((uint32_t)mm_row[e], __float_as_uint((float)mm_val[e]));
+    }
 }
 
 __device__ inline uint32_t bf16_rne(float f) {
@@ -60,21 +66,21 @@ __device__ inline uint32_t bf16_rne(float f) {
     return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
-__global__ void k_ivf_fill(const uint32_t* __restrict__ vals, const int32_t* __restrict__ mm_row,
-                           const double* __restrict__ mm_val, int64_t nnzM, const int64_t* n_dev,
-                           int32_t k_r, int valtype, int32_t* __restrict__ cid,
-                           void* __restrict__ post) {
+// The sorted entries as postings in the stored precision: FP32 {cluster,
+// value}; 16-bit {local cluster id | value << 16}; and each entry's cluster.
+__global__ void k_ivf_store(const uint2* __restrict__ pay, int64_t nnzM, const int64_t* n_dev,
+                            int32_t k_r, int valtype, int32_t* __restrict__ cid,
+                            void* __restrict__ post) {
     nnzM = bounded_count(nnzM, n_dev);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnzM;
          q += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t p = vals[q];
-        const int32_t j = mm_row[p];
-        const double u = mm_val[p];
+        const uint2 e = pay[q];
+        const int32_t j = (int32_t)e.x;
         cid[q] = j;
-        const float f = (float)u;
         if (valtype == IVF_VAL_F32) {
-            reinterpret_cast<uint2*>(post)[q] = make_uint2((uint32_t)j, __float_as_uint(f));
+            reinterpret_cast<uint2*>(post)[q] = e;
         } else {
+            const float f = __uint_as_float(e.y);
             const uint32_t local = (uint32_t)(j % k_r);
             uint32_t h;
             if (valtype == IVF_VAL_BF16) h = bf16_rne(f);
@@ -113,8 +119,8 @@ __global__ void k_desc(const int64_t* ptr, const int32_t* cid, int64_t d, int32_
         const int64_t cnt = hi - lo;
         const int32_t kr = min(k_r, k - r * k_r);
         SliceDesc ds;
-        ds.pos = lo;
-        ds.count = cnt;
+        ds.pos = (int32_t)lo;
+        ds.count = (int32_t)cnt;
         desc[t * R + r] = ds;
         // a dense slab's size is rounded up to whole 128-byte lines, so every
         // slab starts on a line (0.5-0.8 % faster walks at 8M documents)
@@ -131,7 +137,7 @@ __global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, int64_t nslic
     // one that would not fit the slab capacity stays sparse (same scores)
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslices;
          s += (int64_t)gridDim.x * blockDim.x)
-        if (doff[s + 1] > doff[s] && doff[s + 1] <= cap) desc[s].pos = -(doff[s] + 1);
+        if (doff[s + 1] > doff[s] && doff[s + 1] <= cap) desc[s].pos = (int32_t)(-(doff[s] + 1));
 }
 
 template <typename T>
@@ -171,14 +177,16 @@ __global__ void k_slab_scatter(const uint32_t* __restrict__ skeys, const int32_t
 hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s) {
     // a.nnzM: the entry count, or the capacity when a.nnz_dev holds the count
     if (a.nnzM > 0) {
-        k_term_keys<<<capped(a.nnzM), kThreads, 0, s>>>(a.mm_idx, a.keys, a.nnzM, a.nnz_dev);
+        // stable by term: lists in ascending cluster order, the entries' payload
+        // moving with them (no gather through positions afterwards)
+        k_term_entries<<<capped(a.nnzM), kThreads, 0, s>>>(a.mm_idx, a.mm_row, a.mm_val, a.nnzM,
+                                                          a.nnz_dev, a.keys, a.pay);
         HIP_RET(hipGetLastError());
-        HIP_RET(radix_sort_pairs(a.keys, a.vals, a.keys_alt, a.vals_alt, a.nnzM,
-                                 bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, a.iota,
-                                 a.nnz_dev));
-        k_ivf_fill<<<capped(a.nnzM), kThreads, 0, s>>>(a.vals, a.mm_row, a.mm_val, a.nnzM,
-                                                       a.nnz_dev, a.k_r, a.valtype, a.cid,
-                                                       a.post);
+        HIP_RET(radix_sort_pairs_u64(a.keys, a.pay, a.keys_alt, a.pay_alt, a.nnzM,
+                                     bits_for(a.d - 1 > 0 ? a.d - 1 : 1), a.tmp, s, nullptr,
+                                     a.nnz_dev));
+        k_ivf_store<<<capped(a.nnzM), kThreads, 0, s>>>(a.pay, a.nnzM, a.nnz_dev, a.k_r,
+                                                       a.valtype, a.cid, a.post);
         HIP_RET(hipGetLastError());
     }
     k_ivf_ptr<<<grid_for(a.d + 1), kThreads, 0, s>>>(a.keys, a.nnzM, a.nnz_dev, a.d, a.ivf_ptr);

@@ -30,11 +30,14 @@ struct Plan {
 // One (term, cluster range) slice of the inverted file.  pos >= 0: sparse,
 // entries [pos, pos + count) of the posting array; pos < 0: dense slab of the
 // range's width at element offset -pos - 1 of the slab array.  count is the
-// number of clusters of the range holding the term either way.
+// number of clusters of the range holding the term either way.  8 bytes: the
+// posting array holds fewer than 2^31 entries and the slab array fewer than
+// 2^31 - 1 elements (the rebuild keeps a slice sparse rather than exceed it).
 struct SliceDesc {
-    int64_t pos;
-    int64_t count;
+    int32_t pos;
+    int32_t count;
 };
+constexpr int64_t kMaxSlabElems = ((int64_t)1 << 31) - 256;
 
 // Per (object, range) result of the walk.
 struct RangeRec {
@@ -166,7 +169,8 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
 // The same with 8-byte values (the whole payload moves with its key).
 hipError_t radix_sort_pairs_u64(uint32_t* keys, uint2* vals, uint32_t* keys_alt, uint2* vals_alt,
                                 int64_t n, int bits, void* tmp, hipStream_t s,
-                                const uint2* vals_in_first = nullptr);
+                                const uint2* vals_in_first = nullptr,
+                                const int64_t* n_dev = nullptr);
 
 // Plan of the walk for k clusters.
 ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err);

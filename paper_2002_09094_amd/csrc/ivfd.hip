@@ -87,8 +87,8 @@ __global__ void k_ivfd_overlap(const int64_t* __restrict__ x_ptr,
         const int32_t t = x_idx[h];
         m += ivf_ptr[t + 1] - ivf_ptr[t];
     }
-    rec[i * B].m = (int32_t)std::min<int64_t>(m, 0x7fffffff);
-    for (int32_t b = 1; b < B; ++b) rec[i * B + b].m = 0;
+    rec[i].m = (int32_t)std::min<int64_t>(m, 0x7fffffff);
+    for (int32_t b = 1; b < B; ++b) rec[(int64_t)b * n + i].m = 0;
 }
 
 // Largest row norm, FP64 sums of squares in row order.
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kIvfdThreads) void k_ivfd_walk(IvfdArgs a) {
         for (int u = 0; u < 4; ++u) {
             const int64_t o = obj0 + 4 * (int64_t)(tid + kIvfdThreads * g) + u;
             if (o < a.n) {
-                RangeRec* p = a.rec + o * a.B + b;
+                RangeRec* p = a.rec + (int64_t)b * a.n + o;
                 // an integer sum converted once (FP32 rounding) and scaled by 2^-F
                 p->best = (float)best[4 * g + u] * a.inv_scale;
                 p->id = bid[4 * g + u];

@@ -17,7 +17,7 @@ struct WalkArgs {
     int32_t k, k_r, R, chunk, tile_stride;
     int64_t items_per_range;  // ceil(n / chunk)
     Counters* cnt;
-    RangeRec* rec;            // [n * R]
+    RangeRec* rec;            // [R * n], range-major: record (i, r) at r * n + i
 };
 
 struct MergeArgs {
@@ -27,7 +27,7 @@ struct MergeArgs {
     int32_t valtype, certify, force_rescore;
     double fixed_scale;       // > 0: the records hold fixed-point sums (IVFD) of this scale
     double vmax;              // largest object value (the certificate's absolute terms)
-    const RangeRec* rec;
+    const RangeRec* rec;      // [R * n] range-major: record (i, r) at r * n + i
     const int32_t* prev;
     int32_t* assign;
     double* rho;
@@ -47,7 +47,7 @@ struct RescoreArgs {
     int32_t valtype;
     double fixed_scale;       // > 0: `best` is a fixed-point sum (IVFD) of this scale
     double vmax;              // largest object value (the certificate's absolute terms)
-    const RangeRec* rec;      // the walk's range records, [n * w.R] (null: re-walk every range)
+    const RangeRec* rec;      // the walk's range records, [w.R * n] range-major (null: re-walk every range)
     const int32_t* rescore_list;
     const int32_t* prev;
     int32_t* assign;
@@ -91,7 +91,7 @@ struct IvfdArgs {
     int32_t k, R, n_r;        // n_r in {4096, 8192, 16384}
     int32_t B;                // blocks of consecutive means; workgroup = (range, block)
     float scale, inv_scale;   // fixed-point scale 2^F of the products, and 2^-F
-    RangeRec* rec;            // [n * B]: best, id, second (m: launch_ivfd_overlap)
+    RangeRec* rec;            // [B * n], block-major: best, id, second (m: launch_ivfd_overlap)
     unsigned long long* walked;   // entries walked, added
 };
 
@@ -123,10 +123,9 @@ struct IvfArgs {
     const double* mm_val;
     const int32_t* mm_row;
     uint32_t* keys;
-    uint32_t* vals;
     uint32_t* keys_alt;
-    uint32_t* vals_alt;
-    const uint32_t* iota;
+    uint2* pay;          // (cluster, FP32 value bits) per entry, sorted with the keys
+    uint2* pay_alt;
     int64_t* ivf_ptr;    // [d + 1]
     SliceDesc* desc;     // [d * R]
     int64_t* dsz;        // [d * R + 1] dense slab sizes, then their offsets (scanned)
@@ -136,9 +135,11 @@ struct IvfArgs {
     void* tmp;
 };
 
-// Inverted-file rebuild, phase 1: stable sort of the mean entries by term,
-// lists in ascending cluster order with the stored-precision values, slice
-// descriptors and the scanned dense-slab offsets (total at dsz[d * R]).
+// Inverted-file rebuild, phase 1: stable sort of the mean entries by term
+// with their cluster and value as payload, lists in ascending cluster order
+// with the stored-precision values, slice descriptors and the scanned
+// dense-slab offsets (total at dsz[d * R]).  keys/keys_alt and pay/pay_alt
+// hold at least nnzM entries.
 hipError_t launch_build_ivf(IvfArgs& a, hipStream_t s);
 // Phase 2: dense slabs filled (the array holds slab_cap elements; slices that
 // do not fit stay sparse), descriptors of dense slices pointed at them.

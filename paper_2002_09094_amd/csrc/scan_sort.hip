@@ -50,39 +50,67 @@ __device__ inline T block_exclusive_scan(T x, T* sh, T* total) {
     return res;
 }
 
+// Tile totals: consecutive threads read consecutive elements (the sum of
+// integers does not depend on the order).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tile_sums(const T* __restrict__ in, int64_t n,
                                                       T* __restrict__ sums) {
     __shared__ T sh[kBlock / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
     T acc = 0;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i)
-        if (base + i < n) acc += in[base + i];
+    for (int i = 0; i < kItems; ++i) {
+        const int64_t q = base + i * kBlock + threadIdx.x;
+        acc += q < n ? in[q] : (T)0;
+    }
     T total;
     block_exclusive_scan(acc, sh, &total);
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
+// Position of tile element e in the LDS staging array: one pad slot per 16
+// elements, so that the 16-element chunks the threads scan are read and
+// written without bank conflicts.
+__device__ inline int staged(int e) { return e + (e >> 4); }
+
+// Exclusive scan of one tile (plus the tile's offset): the tile is loaded
+// coalesced into LDS, each thread scans its chunk of kItems consecutive
+// elements, and the results go back through LDS to coalesced stores.  in and
+// out may be the same array (each tile is read whole before it is written).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_tile_scan(const T* __restrict__ in, T* __restrict__ out,
                                                       int64_t n, const T* __restrict__ offs) {
     __shared__ T sh[kBlock / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    __shared__ T tile[kTile + kTile / 16];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int e = i * kBlock + threadIdx.x;
+        const int64_t q = base + e;
+        tile[staged(e)] = q < n ? in[q] : (T)0;
+    }
+    __syncthreads();
     T v[kItems];
     T acc = 0;
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-        v[i] = (base + i < n) ? in[base + i] : (T)0;
+        v[i] = tile[staged(threadIdx.x * kItems + i)];
         acc += v[i];
     }
     T total;
-    T run = block_exclusive_scan(acc, sh, &total);
+    T run = block_exclusive_scan(acc, sh, &total);   // synchronises the block
     if (offs) run += offs[blockIdx.x];
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
-        if (base + i < n) out[base + i] = run;
+        tile[staged(threadIdx.x * kItems + i)] = run;
         run += v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        const int e = i * kBlock + threadIdx.x;
+        const int64_t q = base + e;
+        if (q < n) out[q] = tile[staged(e)];
     }
 }
 
@@ -299,9 +327,9 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt,
 
 hipError_t radix_sort_pairs_u64(uint32_t* keys, uint2* vals, uint32_t* keys_alt, uint2* vals_alt,
                                 int64_t n, int bits, void* tmp, hipStream_t s,
-                                const uint2* vals_in_first) {
+                                const uint2* vals_in_first, const int64_t* n_dev) {
     return radix_sort_impl<uint2>(keys, vals, keys_alt, vals_alt, n, bits, tmp, s, vals_in_first,
-                                  nullptr);
+                                  n_dev);
 }
 
 }  // namespace ivf

@@ -391,12 +391,16 @@ __global__ __launch_bounds__(kThreads) void k_norm_parts(UpdateArgs a) {
     const double dn = (double)a.size[j];
     double ss = 0.0, op = 0.0;
     int64_t from = ob;   // a lane's terms ascend, so its old-row cursor only moves on
+    const int64_t row0 = a.cstart[j];
     for (int64_t s = s0 + lane; s < s1; s += kWave) {
         const double sv = seg_value(a.seg_acc, a.seg_t, a.shift, s);
         const double w = sv / dn;
         ss += w * w;
         const int32_t t = a.seg_t[s];
-        const int64_t p = lower_bound_i32(a.old_idx, from, oe, t);
+        // the old row's support differs little from the new one's: term t is
+        // usually at the same rank there; else search what is left of the row
+        int64_t p = ob + (s - row0);
+        if (!(p >= from && p < oe && a.old_idx[p] == t)) p = lower_bound_i32(a.old_idx, from, oe, t);
         from = p;
         if (p < oe && a.old_idx[p] == t) op += a.old_val[p] * sv;
     }

@@ -40,9 +40,9 @@ def walk_bytes(m, nnz, n, ranges, valtype):
     """Algorithmic bytes of one walk launch: every posting entry walked (cluster
     id + value: 8 B for FP32 values, 4 B for 16-bit local ids and values);
     per cluster range, each object nonzero (term id + value, 8 B) with its
-    slice descriptor (two int64, 16 B), the object row pointers (8 B) and the
+    slice descriptor (two int32, 8 B), the object row pointers (8 B) and the
     object's range record written (16 B)."""
-    return ENTRY_BYTES[valtype] * m + ranges * (24 * nnz + 8 * (n + 1) + 16 * n)
+    return ENTRY_BYTES[valtype] * m + ranges * (16 * nnz + 8 * (n + 1) + 16 * n)
 
 
 def iteration_bytes(m, nnz, n, ranges, nnz_means, valtype):

@@ -162,28 +162,34 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
     hist[(int64_t)threadIdx.x * nt + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile of kTile items.  Items are ranked within the
-// tile by digit in their input order (round, wave, lane), placed in LDS in
-// that order, and written out digit run by digit run: consecutive threads
-// write consecutive addresses of a run, where writing each item straight to
-// its bucket touched one cache line per item.  The tile's count of digit d
-// is the difference of consecutive entries of the scanned histogram (laid
-// out digit-major, tile-minor), the last entry's against n.
+// Stable scatter of one tile of kTile items.  Wave w ranks the items w *
+// kTile/4 .. (w + 1) * kTile/4 - 1 of the tile, 64 consecutive ones per
+// round, against counters of its own (peers of a digit found by ballots), so
+// no barrier is needed while ranking; the waves' counts then give every
+// digit's run in the tile, the items are placed in LDS in digit order, and
+// written out run by run: consecutive threads write consecutive addresses of
+// a run, where writing each item straight to its bucket touched one cache
+// line per item.  Ranks follow (wave, round, lane), the input order, so the
+// pass is stable.  The tile's count of digit d is the difference of
+// consecutive entries of the scanned histogram (laid out digit-major,
+// tile-minor), the last entry's against n.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(
     const uint32_t* __restrict__ keys, const V* __restrict__ vals, int64_t n,
     const int64_t* n_dev, int shift, const uint32_t* __restrict__ offs, int64_t nt,
     uint32_t* __restrict__ okeys, V* __restrict__ ovals) {
     constexpr int W = kBlock / kWave;
+    constexpr int R = kTile / kBlock;      // rounds per wave (64 items each)
     n = bounded_count(n, n_dev);
     __shared__ uint32_t s_keys[kTile];
     __shared__ V s_vals[kTile];
-    __shared__ uint32_t run[kDigits];      // next local slot of each digit
+    __shared__ uint32_t wcnt[W][kDigits];  // per wave: its items of each digit so far
     __shared__ uint32_t start[kDigits];    // local start of each digit's run
     __shared__ uint32_t glob[kDigits];     // global start of this tile's run of each digit
-    __shared__ uint32_t wcnt[W][kDigits];
     __shared__ uint32_t sh[kBlock / kWave + 1];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+#pragma unroll
+    for (int q = 0; q < W; ++q) wcnt[q][tid] = 0u;
     {
         const int64_t idx = (int64_t)tid * nt + blockIdx.x;
         const uint32_t g = offs[idx];
@@ -192,18 +198,19 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
         const uint32_t st = block_exclusive_scan<uint32_t>(next - g, sh, &total);
         glob[tid] = g;
         start[tid] = st;
-        run[tid] = st;
     }
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t i = base + (int64_t)r * kBlock + tid;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * (R * kWave);
+    uint32_t key[R], rk[R];
+    V val[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = base + r * kWave + lane;
         const bool valid = i < n;
-        uint32_t key = valid ? keys[i] : 0u;
-        V val{};
-        if (valid) val = vals[i];
-        const uint32_t d = (key >> shift) & (kDigits - 1);
+        key[r] = valid ? keys[i] : 0u;
+        if (valid) val[r] = vals[i];
+        const uint32_t d = (key[r] >> shift) & (kDigits - 1);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -211,40 +218,43 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-#pragma unroll
-        for (int q = 0; q < W; ++q) wcnt[q][tid] = 0u;
-        __syncthreads();
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        {
-            uint32_t acc = run[tid];
-#pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const uint32_t t = wcnt[q][tid];
-                wcnt[q][tid] = acc;
-                acc += t;
-            }
-            run[tid] = acc;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = wcnt[w][d] + rank;
-            if (pos < (uint32_t)kTile) {
-                s_keys[pos] = key;
-                s_vals[pos] = val;
-            }
-        }
-        __syncthreads();
+        const uint32_t before = (uint32_t)__popcll(peers & lt);
+        const uint32_t c = wcnt[w][d];   // read by every peer before the first of them adds
+        rk[r] = valid ? c + before : 0xffffffffu;
+        if (valid && before == 0) wcnt[w][d] = c + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
+    {   // per digit: the waves' offsets inside its run
+        uint32_t acc = start[tid];
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const uint32_t t = wcnt[q][tid];
+            wcnt[q][tid] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (rk[r] != 0xffffffffu) {
+            const uint32_t d = (key[r] >> shift) & (kDigits - 1);
+            const uint32_t pos = wcnt[w][d] + rk[r];
+            if (pos < (uint32_t)kTile) {
+                s_keys[pos] = key[r];
+                s_vals[pos] = val[r];
+            }
+        }
+    }
+    __syncthreads();
     // the tile in digit order: runs of consecutive addresses
-    const int64_t items = std::min<int64_t>(kTile, std::max<int64_t>(0, n - base));
+    const int64_t tbase = (int64_t)blockIdx.x * kTile;
+    const int64_t items = std::min<int64_t>(kTile, std::max<int64_t>(0, n - tbase));
     for (int p = tid; p < items; p += kBlock) {
-        const uint32_t key = s_keys[p];
-        const uint32_t d = (key >> shift) & (kDigits - 1);
+        const uint32_t k2 = s_keys[p];
+        const uint32_t d = (k2 >> shift) & (kDigits - 1);
         const int64_t pos = (int64_t)glob[d] + (p - (int64_t)start[d]);
         if (pos >= 0 && pos < n) {
-            okeys[pos] = key;
+            okeys[pos] = k2;
             ovals[pos] = s_vals[p];
         }
     }

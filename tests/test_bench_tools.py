@@ -86,10 +86,10 @@ def test_trace_summary_lists_launches_and_the_steady_state_average(tmp_path):
 
 def test_algorithmic_bytes_and_the_stale_counter_rule(tmp_path, monkeypatch):
     # 8 B per FP32 posting entry (id + value), 4 B for 16-bit values; per
-    # cluster range: 24 B per object nonzero (id, value, slice descriptor),
+    # cluster range: 16 B per object nonzero (id, value, 8-byte slice descriptor),
     # 8 B per row pointer, 16 B per range record written
-    assert bench.walk_bytes(10, 3, 2, 1, "f32") == 80 + 72 + 24 + 32
-    assert bench.walk_bytes(10, 3, 2, 4, "bf16") == 40 + 4 * (72 + 24 + 32)
+    assert bench.walk_bytes(10, 3, 2, 1, "f32") == 80 + 48 + 24 + 32
+    assert bench.walk_bytes(10, 3, 2, 4, "bf16") == 40 + 4 * (48 + 24 + 32)
     assert (bench.iteration_bytes(10, 3, 2, 1, 5, "f32")
             == bench.walk_bytes(10, 3, 2, 1, "f32") + 16 + 48 + 5 * 32)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))

@@ -808,8 +808,8 @@ ivf_status alloc_handle(ivf_handle* h) {
     HIPCHK(h, dalloc(&h->part, kObjBlocks));
     HIPCHK(h, dalloc(&h->dscal, 4));
     HIPCHK(h, walk_set_lds_limit(kLdsBytes));
-    h->walk_grid = occupancy_grid(h->cus, walk_kernel_ptr(h->opt.valtype), h->plan.waves,
-                                  h->plan.lds_bytes);
+    h->walk_grid = occupancy_grid(h->cus, walk_kernel_ptr(h->opt.valtype, h->plan.k_r),
+                                  h->plan.waves, h->plan.lds_bytes);
     plan_rescore(h);
     return IVF_OK;
 }
@@ -1072,7 +1072,7 @@ ivf_status batch_plan(ivf_batch* b, int32_t kr_max, int32_t waves) {
     b->kr_max = kr_max;
     b->waves = waves;
     b->tile_stride = stride;
-    b->grid = occupancy_grid(b->cus, walk_batch_kernel_ptr(b->opt.valtype), waves,
+    b->grid = occupancy_grid(b->cus, walk_batch_kernel_ptr(b->opt.valtype, stride), waves,
                              waves * stride * 4);
     drop_graphs(b);
     return upload_args(b);

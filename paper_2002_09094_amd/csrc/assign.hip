@@ -3,11 +3,12 @@
 //
 //   k_walk     For each (cluster range, object): stream the object's CSR
 //              nonzeros, gather the range's slice of each term's posting list
-//              and accumulate x_t * m_jt into a per-wave FP32 LDS score
-//              tile (one wave owns one tile, so every slot is accumulated in
-//              ascending term order); a fused wave-wide pass then extracts the
-//              range's top-1 (lowest id on equal scores) and top-2 and clears
-//              the tile for the next object.
+//              and accumulate x_t * m_jt into the wave's own FP32 score tile
+//              (ranges of up to 1,024 clusters with FP32 values: dense slabs
+//              into registers, sparse slices into LDS, the two sums added once;
+//              otherwise one LDS tile in ascending term order); a fused
+//              wave-wide pass then extracts the range's top-1 (lowest id on
+//              equal scores) and top-2 and clears the tile for the next object.
 //   k_merge    Per object: merge the ranges' records, certify the FP32 argmax
 //              with the rounding-error bound, else queue the object for FP64.
 //   k_rescore  Per queued object: walk it again in FP32, keep the clusters the
@@ -326,6 +327,141 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
     return m;
 }
 
+// FP32 ranges of at most kRegClusters clusters keep the object's scores in
+// registers: slots 4g .. 4g + 3 of group g = u * 64 + lane are lane's acc[u].
+// A dense slab is added there with no LDS traffic; sparse slices still
+// scatter into the wave's LDS tile, which is added into the registers once
+// per object.  Every slot is then the sum of its dense products (ascending
+// terms) plus the sum of its sparse products (ascending terms): another
+// summation order of the same rounded products, so the certification bound,
+// which holds for any order, is unchanged.  At 8M documents x k = 10,000
+// (fixed means) the walk took 866 ms against 906 ms with the whole tile in
+// LDS.  Its sparse loads are ordinary ones: the non-temporal hint that helps
+// the LDS-tile walk made this one slower (906 ms).
+constexpr int kRegGroups = 4;
+constexpr int32_t kRegClusters = kRegGroups * kWave * 4;
+
+__device__ inline void walk_dense_reg(const float4* __restrict__ S, int32_t kr4, float v,
+                                      float4 (&acc)[kRegGroups], int lane) {
+    float4 x[kRegGroups];
+#pragma unroll
+    for (int u = 0; u < kRegGroups; ++u) {
+        const int32_t g = u * kWave + lane;
+        x[u] = g < kr4 ? S[g] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kRegGroups; ++u) {   // o + v * m, a product and a sum
+        acc[u].x = acc[u].x + v * x[u].x;
+        acc[u].y = acc[u].y + v * x[u].y;
+        acc[u].z = acc[u].z + v * x[u].z;
+        acc[u].w = acc[u].w + v * x[u].w;
+    }
+}
+
+// Object i against range r: dense slabs into acc, sparse slices into the LDS
+// tile (`sparse` tells whether any was).  Returns the entries walked.
+__device__ inline int32_t accumulate_object_reg(const WalkArgs& a, int64_t i, int r, int32_t base,
+                                                int32_t kr, float* tile,
+                                                float4 (&acc)[kRegGroups], bool& sparse,
+                                                int lane) {
+    const int64_t hb = a.x_ptr[i], he = a.x_ptr[i + 1];
+    const int32_t kr4 = (kr + 3) >> 2;
+    int32_t m = 0;
+    for (int64_t h0 = hb; h0 < he; h0 += kWave) {
+        const int cnt = (int)min((int64_t)kWave, he - h0);
+        float v = 0.f;
+        int32_t pos = 0, count = 0;
+        if (lane < cnt) {
+            const int32_t t = a.x_idx[h0 + lane];
+            v = a.x_val[h0 + lane];
+            const SliceDesc ds = a.desc[(int64_t)t * a.R + r];
+            pos = ds.pos;
+            count = ds.count;
+        }
+        for (int hh = 0; hh < cnt; ++hh) {
+            const int64_t p = rl32(pos, hh), cn = rl32(count, hh);
+            const float vv = rlf(v, hh);
+            m += (int32_t)cn;
+            if (p >= 0) {
+                sparse = true;
+                walk_slice<IVF_VAL_F32, false>(reinterpret_cast<const uint2*>(a.post), p, p + cn,
+                                               vv, tile, base, lane);
+            } else {
+                walk_dense_reg(slab_at<IVF_VAL_F32>(a, p), kr4, vv, acc, lane);
+            }
+        }
+    }
+    return m;
+}
+
+// One work item of an FP32 range of at most kRegClusters clusters: per object
+// the register walk, the sparse sums added (the LDS tile cleared), top-1 and
+// top-2 over the registers and the range record.
+__device__ inline void walk_item_reg(const WalkArgs& a, int64_t w, float* tile, int lane) {
+    const int r = (int)(w / a.items_per_range);
+    const int64_t c = w - (int64_t)r * a.items_per_range;
+    const int32_t base = r * a.k_r;
+    const int32_t kr = min(a.k_r, a.k - base);
+    const int32_t kr4 = (kr + 3) >> 2;
+    const int64_t i0 = c * a.chunk;
+    const int64_t i1 = min(a.n, i0 + a.chunk);
+    float4* t4 = reinterpret_cast<float4*>(tile);
+    for (int64_t i = i0; i < i1; ++i) {
+        float4 acc[kRegGroups];
+#pragma unroll
+        for (int u = 0; u < kRegGroups; ++u) acc[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool sparse = false;
+        const int32_t m = accumulate_object_reg(a, i, r, base, kr, tile, acc, sparse, lane);
+        if (sparse) {
+#pragma unroll
+            for (int u = 0; u < kRegGroups; ++u) {
+                const int32_t g = u * kWave + lane;
+                if (g < kr4) {
+                    const float4 q = t4[g];
+                    t4[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    acc[u].x = acc[u].x + q.x;
+                    acc[u].y = acc[u].y + q.y;
+                    acc[u].z = acc[u].z + q.z;
+                    acc[u].w = acc[u].w + q.w;
+                }
+            }
+        }
+        // top-2 in ascending slot order per lane, then across lanes
+        float b = 0.f, s2 = 0.f;
+        int32_t id = -1;
+#pragma unroll
+        for (int u = 0; u < kRegGroups; ++u) {
+            const int32_t s0 = (u * kWave + lane) * 4;
+            const float x[4] = {acc[u].x, acc[u].y, acc[u].z, acc[u].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (s0 + e < kr) {
+                    if (x[e] > b) {
+                        s2 = fmaxf(s2, b);
+                        b = x[e];
+                        id = s0 + e;
+                    } else {
+                        s2 = fmaxf(s2, x[e]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) {
+            const float ob = __shfl_xor(b, o, kWave);
+            const int32_t oid = __shfl_xor(id, o, kWave);
+            const float os = __shfl_xor(s2, o, kWave);
+            top2_combine(b, id, s2, ob, oid, os);
+        }
+        RangeRec rec;
+        rec.best = b;
+        rec.id = id >= 0 ? base + id : -1;
+        rec.second = s2;
+        rec.m = m;
+        a.rec[(int64_t)r * a.n + i] = rec;
+    }
+}
+
 // One work item: `chunk` consecutive objects against cluster range r, each
 // walked into the wave's tile, its range record written and the tile cleared.
 template <int VT, bool NT = false>
@@ -391,11 +527,18 @@ __device__ inline int64_t claim_item(unsigned long long* ctr, int lane) {
 
 // Waves per SIMD the walk is compiled for (the register budget): 8 for 16-bit
 // values (about a dozen registers spill; 7, without spills, measured no faster);
-// the FP32 walk keeps 6 (8 measured 18 % slower: it is bound by L2 capacity,
-// not by latency hiding).
-template <int VT>
+// 6 for the FP32 LDS-tile walk (8 measured 18 % slower: it is bound by L2
+// capacity, not by latency hiding); 7 for the FP32 register walk, whose
+// registers then hold 3 workgroups of 8 waves as at 6 (28 waves in 4-wave
+// workgroups and 32 at 8 per SIMD were no faster).
+constexpr int walk_waves_per_eu(int vt, bool reg) {
+    return vt != IVF_VAL_F32 ? 8 : (reg ? 7 : 6);
+}
+
+// REG: the FP32 register walk (every range of at most kRegClusters clusters).
+template <int VT, bool REG>
 __global__ __launch_bounds__(kWave * kMaxWaves)
-__attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(WalkArgs a) {
+__attribute__((amdgpu_waves_per_eu(walk_waves_per_eu(VT, REG), 8))) void k_walk(WalkArgs a) {
     extern __shared__ float4 lds4[];
     const int lane = lane_id();
     // wave index made provably uniform, so every loop below has uniform bounds
@@ -411,7 +554,8 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(W
     for (;;) {
         const int64_t w = claim_item(&a.cnt->work, lane);
         if (w >= total) break;
-        walk_item<VT, VT == IVF_VAL_F32>(a, w, tile, lane);
+        if constexpr (REG) walk_item_reg(a, w, tile, lane);
+        else walk_item<VT, VT == IVF_VAL_F32>(a, w, tile, lane);
     }
 }
 
@@ -423,9 +567,12 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 8, 8))) void k_walk(W
 // (a working set many times one range's); claiming keeps all waves within
 // one window of consecutive items.  Every claim advances the counter, so a
 // wave leaves after at most total + 1 claims.  The FP32 kernel is compiled
-// for 6 waves per SIMD like the single walk (1.2 % faster than 7 on the
-// 96-instance mix), the 16-bit ones for 7.
-template <int VT>
+// for 6 waves per SIMD (1.2 % faster than 7 on the 96-instance mix), the
+// 16-bit ones for 7.  FP32 instances take the register walk exactly when a
+// single handle of the same plan would (ranges of at most kRegClusters), so
+// a batch computes each instance's scores as its own handle does; ALLREG
+// marks a batch whose instances all do.
+template <int VT, bool ALLREG>
 __global__ __launch_bounds__(kWave * kMaxWaves)
 __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 7, 8))) void k_walk_batch(const WalkArgs* __restrict__ args,
                                                                   const int64_t* __restrict__ item_off,
@@ -446,7 +593,14 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 7, 8))) void k_walk_b
             if (item_off[mid] <= w) lo = mid; else hi = mid;
         }
         const WalkArgs a = args[lo];
-        walk_item<VT>(a, w - item_off[lo], tile, lane);
+        if constexpr (VT == IVF_VAL_F32 && ALLREG) {
+            walk_item_reg(a, w - item_off[lo], tile, lane);
+        } else if constexpr (VT == IVF_VAL_F32) {
+            if (a.k_r <= kRegClusters) walk_item_reg(a, w - item_off[lo], tile, lane);
+            else walk_item<VT>(a, w - item_off[lo], tile, lane);
+        } else {
+            walk_item<VT>(a, w - item_off[lo], tile, lane);
+        }
     }
 }
 
@@ -562,9 +716,12 @@ __device__ inline double exact_score(const RescoreArgs& a, int64_t hb, int64_t h
 // The walk's record of each range bounds its scores: its best is the range
 // winner's, its second the largest of every other cluster's.  A range whose
 // best cannot be a candidate is skipped; one whose second cannot be holds one
-// candidate, its winner; any other range is walked again in FP32 (the same
-// code, so the tile holds the scores the walk had) and its candidates read
-// from the tile.  Without records (another walk's), every range is walked.
+// candidate, its winner; any other range is walked again in FP32 into the
+// LDS tile and its candidates read from the tile.  Without records (another
+// walk's), every range is walked.  Where the main walk kept a range's scores
+// in registers, the walk again adds the same products in another order, so
+// its scores may differ from the walk's in the last bits; each is within its
+// own bound of the FP64 score, which is all the rule above uses.
 template <int VT>
 __global__ __launch_bounds__(kWave * kMaxWaves) void k_rescore(RescoreArgs a) {
     extern __shared__ float4 lds4[];
@@ -711,12 +868,14 @@ hipError_t launch_clear_counters(Counters* c, hipStream_t s) {
 hipError_t launch_walk(const WalkArgs& a, int valtype, int waves, int lds_bytes, int grid,
                        hipStream_t s) {
     const dim3 blk(kWave * waves);
-    if (valtype == IVF_VAL_F32)
-        k_walk<IVF_VAL_F32><<<grid, blk, lds_bytes, s>>>(a);
+    if (valtype == IVF_VAL_F32 && a.k_r <= kRegClusters)
+        k_walk<IVF_VAL_F32, true><<<grid, blk, lds_bytes, s>>>(a);
+    else if (valtype == IVF_VAL_F32)
+        k_walk<IVF_VAL_F32, false><<<grid, blk, lds_bytes, s>>>(a);
     else if (valtype == IVF_VAL_BF16)
-        k_walk<IVF_VAL_BF16><<<grid, blk, lds_bytes, s>>>(a);
+        k_walk<IVF_VAL_BF16, false><<<grid, blk, lds_bytes, s>>>(a);
     else
-        k_walk<IVF_VAL_F16><<<grid, blk, lds_bytes, s>>>(a);
+        k_walk<IVF_VAL_F16, false><<<grid, blk, lds_bytes, s>>>(a);
     return hipGetLastError();
 }
 
@@ -726,34 +885,52 @@ hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int3
     const dim3 blk(kWave * waves);
     const size_t lds = (size_t)waves * tile_stride * 4;
     k_zero_u64<<<1, 64, 0, s>>>(work);
-    if (valtype == IVF_VAL_F32)
-        k_walk_batch<IVF_VAL_F32><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride, work);
+    if (valtype == IVF_VAL_F32 && tile_stride <= kRegClusters)
+        k_walk_batch<IVF_VAL_F32, true><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride,
+                                                               work);
+    else if (valtype == IVF_VAL_F32)
+        k_walk_batch<IVF_VAL_F32, false><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride,
+                                                                work);
     else if (valtype == IVF_VAL_BF16)
-        k_walk_batch<IVF_VAL_BF16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride, work);
+        k_walk_batch<IVF_VAL_BF16, false><<<grid, blk, lds, s>>>(args, item_off, count,
+                                                                 tile_stride, work);
     else
-        k_walk_batch<IVF_VAL_F16><<<grid, blk, lds, s>>>(args, item_off, count, tile_stride, work);
+        k_walk_batch<IVF_VAL_F16, false><<<grid, blk, lds, s>>>(args, item_off, count,
+                                                                tile_stride, work);
     return hipGetLastError();
 }
 
-const void* walk_kernel_ptr(int valtype) {
-    if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32>);
-    if (valtype == IVF_VAL_BF16) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_BF16>);
-    return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F16>);
+const void* walk_kernel_ptr(int valtype, int32_t k_r) {
+    if (valtype == IVF_VAL_F32 && k_r <= kRegClusters)
+        return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32, true>);
+    if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F32, false>);
+    if (valtype == IVF_VAL_BF16)
+        return reinterpret_cast<const void*>(&k_walk<IVF_VAL_BF16, false>);
+    return reinterpret_cast<const void*>(&k_walk<IVF_VAL_F16, false>);
 }
 
-const void* walk_batch_kernel_ptr(int valtype) {
-    if (valtype == IVF_VAL_F32) return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F32>);
-    if (valtype == IVF_VAL_BF16) return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_BF16>);
-    return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F16>);
+const void* walk_batch_kernel_ptr(int valtype, int32_t tile_stride) {
+    if (valtype == IVF_VAL_F32 && tile_stride <= kRegClusters)
+        return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F32, true>);
+    if (valtype == IVF_VAL_F32)
+        return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F32, false>);
+    if (valtype == IVF_VAL_BF16)
+        return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_BF16, false>);
+    return reinterpret_cast<const void*>(&k_walk_batch<IVF_VAL_F16, false>);
 }
 
 hipError_t walk_set_lds_limit(int lds_bytes) {
     // the attribute is per kernel and shared by every handle: allow the whole
     // LDS, each launch asks for what its tiles need
     lds_bytes = kLdsBytes;
-    const void* ks[] = {walk_kernel_ptr(IVF_VAL_F32), walk_kernel_ptr(IVF_VAL_BF16),
-                        walk_kernel_ptr(IVF_VAL_F16), walk_batch_kernel_ptr(IVF_VAL_F32),
-                        walk_batch_kernel_ptr(IVF_VAL_BF16), walk_batch_kernel_ptr(IVF_VAL_F16)};
+    const void* ks[] = {walk_kernel_ptr(IVF_VAL_F32, kRegClusters),
+                        walk_kernel_ptr(IVF_VAL_F32, kRegClusters + 1),
+                        walk_kernel_ptr(IVF_VAL_BF16, 0),
+                        walk_kernel_ptr(IVF_VAL_F16, 0),
+                        walk_batch_kernel_ptr(IVF_VAL_F32, kRegClusters),
+                        walk_batch_kernel_ptr(IVF_VAL_F32, kRegClusters + 1),
+                        walk_batch_kernel_ptr(IVF_VAL_BF16, 0),
+                        walk_batch_kernel_ptr(IVF_VAL_F16, 0)};
     for (const void* k : ks) {
         hipError_t e =
             hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);

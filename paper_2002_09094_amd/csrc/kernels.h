@@ -59,8 +59,10 @@ struct RescoreArgs {
 
 hipError_t launch_clear_counters(Counters* c, hipStream_t s);
 hipError_t walk_set_lds_limit(int lds_bytes);
-const void* walk_kernel_ptr(int valtype);
-const void* walk_batch_kernel_ptr(int valtype);
+// The walk kernel a plan launches: FP32 ranges of up to 1,024 clusters take
+// the register walk (for a batch: every instance within tile_stride).
+const void* walk_kernel_ptr(int valtype, int32_t k_r);
+const void* walk_batch_kernel_ptr(int valtype, int32_t tile_stride);
 // Walk of many instances in one persistent launch (args, item_off: device;
 // work: a device counter the launch resets and the waves claim items from).
 hipError_t launch_walk_batch(const WalkArgs* args, const int64_t* item_off, int32_t count,

@@ -166,6 +166,36 @@ def test_cert_bound_holds_for_emulated_fp32_scores(vt, fused):
         assert err <= Fraction(c) * exact + Fraction(a), (vt, trial, float(err), float(exact))
 
 
+def test_cert_bound_holds_for_split_fp32_sums():
+    """The FP32 register walk sums an object's dense-slab products and its
+    sparse-slice products separately (each in ascending term order) and adds
+    the two once.  Emulate that order on the CPU, with an arbitrary split of
+    the terms, and check the same bound against the exact score, including
+    the adversarial magnitudes of the sequential test."""
+    rng = np.random.default_rng(29)
+    for trial in range(300):
+        nt = int(rng.integers(1, 400))
+        v = rng.uniform(0, 1, nt) ** rng.uniform(1, 8)
+        v = (v / np.linalg.norm(v)).astype(np.float32)
+        v[v == 0] = np.float32(1e-30)
+        u = (rng.uniform(0, 1, nt) ** rng.uniform(1, 12)) * 10.0 ** -rng.uniform(0, 6)
+        us = u.astype(np.float32)
+        dense = rng.uniform(0, 1, nt) < rng.uniform(0, 1)
+        acc_d = np.float32(0)
+        acc_s = np.float32(0)
+        for t in range(nt):
+            p = np.float32(v[t] * us[t])
+            if dense[t]:
+                acc_d = np.float32(acc_d + p)
+            else:
+                acc_s = np.float32(acc_s + p)
+        acc = np.float32(acc_d + acc_s)
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(v, u))
+        c, a, _ = ivf.cert_bound("f32", nt, float(v.max()))
+        err = abs(Fraction(float(acc)) - exact)
+        assert err <= Fraction(c) * exact + Fraction(a), (trial, float(err), float(exact))
+
+
 def _stored(vt, u):
     u32 = u.astype(np.float32)
     if vt == "bf16":

@@ -44,7 +44,26 @@ def _instances():
     return out
 
 
-def _run_against_singles(inst, iters, batch_opts, single_opts, slack=None):
+def _same_fp32_stats(bs, ss, n, exact):
+    """Statistics read from the FP32 tile scores.  With the same plan (range
+    width and slab threshold) the batch computes every score as the single
+    handle does, bit for bit.  Across plans, the FP32 register walk adds an
+    object's dense-slab and sparse-slice products in two sums, and which
+    slices are dense depends on the plan, so scores may differ in the last
+    bits: the objective then agrees within both bounds, and the counts still
+    partition the objects."""
+    if exact:
+        for key in ("certified", "rescored"):
+            assert bs[key] == ss[key], key
+        assert bs["objective"] == ss["objective"]
+        return
+    for st in (bs, ss):
+        assert st["certified"] + st["rescored"] + st["zero_overlap"] == n
+    tol = bs["objective_bound"] + ss["objective_bound"]
+    assert abs(bs["objective"] - ss["objective"]) <= tol * ss["objective"] + 1e-300
+
+
+def _run_against_singles(inst, iters, batch_opts, single_opts, slack=None, exact_fp32=True):
     b = ivf.IVFBatch([(dx[0], dx[1], dx[2], d) for (_, dx, d, _, _) in inst],
                      [k for (_, _, _, k, _) in inst], **batch_opts)
     if slack is not None:
@@ -67,9 +86,9 @@ def _run_against_singles(inst, iters, batch_opts, single_opts, slack=None):
             ga, gs = ba[i].cpu().numpy(), sa[i].cpu().numpy()
             mism = np.nonzero(ga != gs)[0]
             assert len(mism) == 0, ("iteration", r, "instance", i, mism[:10])
-            for key in ("changed", "mult_adds", "certified", "rescored", "zero_overlap"):
+            for key in ("changed", "mult_adds", "zero_overlap"):
                 assert bst[i][key] == s1[key], (r, i, key, bst[i][key], s1[key])
-            assert bst[i]["objective"] == s1["objective"]
+            _same_fp32_stats(bst[i], s1, ga.shape[0], exact_fp32)
             assert bst[i]["objective_exact"] == s2["objective_exact"]
             assert bst[i]["empty_clusters"] == s2["empty_clusters"]
             assert bst[i]["nnz_means"] == s2["nnz_means"]
@@ -86,9 +105,11 @@ def _run_against_singles(inst, iters, batch_opts, single_opts, slack=None):
 
 
 def test_batch_equals_single_handles_with_autotuned_tiles():
+    # the tuner picks the batch's tiles and slab threshold, the single handles
+    # keep their defaults: FP32 statistics agree within the bound
     inst = _instances()
     print("instances", len(inst), flush=True)
-    plans, plan = _run_against_singles(inst, 7, {}, {})
+    plans, plan = _run_against_singles(inst, 7, {}, {}, exact_fp32=False)
     print("plan", plan, flush=True)
     assert plans[0]["graphs"] == 0 and plans[1]["tuned"] == 1
     assert plans[2]["graphs"] == 1 and plan["captures"] >= 1
@@ -104,6 +125,17 @@ def test_batch_overflow_recovery_and_fixed_tiles():
     print("plan", plan, flush=True)
     assert plan["tuned"] == 0 and plan["kr_max"] == 64 and plan["waves"] == 3
     assert plan["recoveries"] >= 1 and plan["captures"] >= 2
+
+
+def test_batch_mixed_tile_kinds_equal_single_handles():
+    # 2,560-wide tiles: instances whose ranges fit 1,024 clusters take the
+    # FP32 register walk, the others the LDS-tile walk, in one launch; with
+    # the same plan every statistic equals the single handle's bit for bit
+    inst = _instances()
+    opts = {"cluster_range": 2560, "waves_per_wg": 4, "dense_threshold": 0.35}
+    plans, plan = _run_against_singles(inst, 4, opts, opts)
+    assert plan["kr_max"] == 2560 and plan["tuned"] == 0
+    assert any(k > 1024 for (_, _, _, k, _) in inst) and any(k <= 1024 for (_, _, _, k, _) in inst)
 
 
 @pytest.mark.parametrize("valtype", ["bf16", "f16"])
@@ -200,9 +232,11 @@ def test_batch_at_the_many_instance_workload_scale():
             got = sa.cpu().numpy()
             h, bs = hist[r][i]
             assert digest(got) == h, (w.name, rs, r)
-            for key in ("changed", "mult_adds", "certified", "rescored", "zero_overlap"):
+            for key in ("changed", "mult_adds", "zero_overlap"):
                 assert bs[key] == s1[key], (w.name, rs, r, key)
-            assert bs["objective"] == s1["objective"]
+            # the batch's plan (tuned tiles and threshold) is not the single
+            # handle's default
+            _same_fp32_stats(bs, s1, w.n, False)
             flags = km.get_scores()[4].cpu().numpy()
             resc = np.nonzero(flags & 2)[0]
             if len(resc):

@@ -53,9 +53,10 @@ def iteration_bytes(m, nnz, n, ranges, nnz_means, valtype):
             + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
 
 
-def kernel_hash(sources=("assign.hip", "invfile.hip")):
-    """Hash of a kernel's sources and the shared headers: the walk's kernels
-    and the inverted-file layout they read (slabs, postings) by default."""
+def kernel_hash(sources=("assign.hip", "invfile.hip", "api.hip")):
+    """Hash of a kernel's sources and the shared headers: by default the
+    walk's kernels, the inverted-file layout they read (slabs, postings) and
+    the planner that picks their plan."""
     h = hashlib.sha256()
     for f in (*sources, "kernels.h", "ivf_internal.h"):
         with open(os.path.join(ROOT, "paper_2002_09094_amd", "csrc", f), "rb") as fh:
@@ -379,8 +380,10 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         f.write("\n".join(lines) + "\n")
 
 
-KERNEL_SOURCE = {"k_walk": ("assign.hip", "invfile.hip"),
-                 "k_walk_batch": ("assign.hip", "invfile.hip"),
+# the walk's counters also depend on the plan (range width, slab threshold),
+# which the planner in api.hip chooses
+KERNEL_SOURCE = {"k_walk": ("assign.hip", "invfile.hip", "api.hip"),
+                 "k_walk_batch": ("assign.hip", "invfile.hip", "api.hip"),
                  "k_ivfd_walk": ("ivfd.hip",)}
 
 

@@ -94,7 +94,9 @@ typedef struct {
     int32_t force_rescore;  /* test hook: 1 = treat every object as uncertified */
     float dense_threshold;  /* a (term, range) slice holding at least this fraction of the
                                range's clusters is stored as a dense slab (zeros for absent
-                               clusters, no ids); 0: default 0.35; > 1: never dense */
+                               clusters, no ids); 0: default, 0.45 for FP32 values in ranges
+                               of at most 1,024 clusters (the register walk), else 0.35;
+                               > 1: never dense */
     void* stream;           /* hipStream_t; NULL = the null stream */
     int32_t full_update;    /* 1: every ivf_update runs the full reduction over all object
                                entries; 0 (default): when few objects changed cluster since
@@ -374,8 +376,9 @@ const char* ivf_status_str(int32_t status);
  * Tiles: with opts->cluster_range == 0 an autotuner times the batched walk
  * over a few (clusters per tile, waves per workgroup) shapes on the means of
  * the second iteration and keeps the fastest; otherwise the given shape is used.
- * When it runs and opts->dense_threshold is 0, it then times a few dense-slab
- * thresholds (0.35, 0.5, 0.65) on the chosen shape and keeps the fastest.
+ * The shapes are timed at each instance's default dense-slab threshold.  When
+ * the tuner runs and opts->dense_threshold is 0, it then times the thresholds
+ * 0.35, 0.45, 0.5 and 0.65 on the chosen shape and keeps the fastest.
  * After the walk, the instances' merges and updates run on 4 streams the
  * batch creates (default priority), forked from and joined back into the
  * batch stream within every iteration, so work the caller enqueues on the
@@ -452,7 +455,7 @@ ivf_status ivf_batch_get_tuning(const ivf_batch* b, int32_t cap, int32_t* shapes
  * timed on its chosen shape (host outputs), as ivf_batch_get_tuning: *count
  * receives how many (0 before it ran, when the shape was given or when
  * opts->dense_threshold was set), thetas[i] the threshold, ms[i] the batched
- * walk's device time with it; the first is the default the shapes were timed at.
+ * walk's device time with it, in the order timed (0.35, 0.45, 0.5, 0.65).
  */
 ivf_status ivf_batch_get_threshold_tuning(const ivf_batch* b, int32_t cap, float* thetas,
                                           float* ms, int32_t* count);

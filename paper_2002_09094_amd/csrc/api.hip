@@ -375,9 +375,15 @@ ivf_status check_value_range(ivf_handle* h, double mmax) {
 }
 
 // Default share of a range's clusters from which a (term, range) slice is a
-// dense slab: measured fastest at 8M documents x k = 10,000 (FP32: 936 ms
-// against 962 ms at 0.5 and 995 ms at 0.2; BF16 670 against 677 ms; FP16 flat)
-constexpr float kDenseDefault = 0.35f;
+// dense slab.  The LDS-tile walks: 0.35, measured fastest at 8M documents x
+// k = 10,000 (FP32 LDS-tile walk: 936 ms against 962 ms at 0.5 and 995 ms at
+// 0.2; BF16 670 against 677 ms; FP16 flat).  The FP32 register walk: 0.45
+// (same workload, fixed means after 4 and after 8 iterations: 847 and 849 ms
+// against 865 and 895 ms at 0.35, 881 and 902 ms at 0.5 and 0.48; on the
+// 2M-document k = 50,000 workload 1,509 against 1,492 ms at 0.35).
+float dense_default(int32_t valtype, int32_t k_r) {
+    return (valtype == IVF_VAL_F32 && k_r <= kRegClusters) ? 0.45f : 0.35f;
+}
 
 IvfArgs ivf_args(ivf_handle* h, int b) {
     IvfArgs a{};
@@ -386,7 +392,8 @@ IvfArgs ivf_args(ivf_handle* h, int b) {
     a.k_r = h->plan.k_r;
     a.R = h->plan.R;
     a.valtype = h->opt.valtype;
-    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold : kDenseDefault;
+    a.dense_threshold = h->opt.dense_threshold > 0.f ? h->opt.dense_threshold
+                                                     : dense_default(h->opt.valtype, h->plan.k_r);
     a.mm_idx = h->mm_idx[b];
     a.mm_val = h->mm_val[b];
     a.mm_row = h->mm_row[b];
@@ -1118,11 +1125,12 @@ ivf_status batch_autotune(ivf_batch* b) {
     if (b->opt.dense_threshold > 0.f) return batch_plan(b, cand[bi][0], cand[bi][1]);
     // A higher threshold stores fewer, fuller slabs: fewer zero bytes read,
     // more (id, value) entries.  Mixes of many small instances measured
-    // fastest above the default chosen for one large instance.
-    static const float thetas[] = {0.5f, 0.65f};
-    float t_best = kDenseDefault;
-    b->tune_theta.push_back(kDenseDefault);
-    b->tune_theta_ms.push_back(best);
+    // fastest above the default chosen for one large instance.  The shapes
+    // were timed at each instance's default (dense_default); the thresholds
+    // are then timed on the chosen shape, each for every instance.
+    static const float thetas[] = {0.35f, 0.45f, 0.5f, 0.65f};
+    float t_best = thetas[0];
+    best = 3.4e38f;
     for (float t : thetas) {
         for (ivf_handle* h : b->h) h->opt.dense_threshold = t;
         ivf_status st = batch_plan(b, cand[bi][0], cand[bi][1]);

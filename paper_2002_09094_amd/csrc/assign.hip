@@ -339,7 +339,7 @@ __device__ inline int32_t accumulate_object(const WalkArgs& a, int64_t i, int r,
 // LDS.  Its sparse loads are ordinary ones: the non-temporal hint that helps
 // the LDS-tile walk made this one slower (906 ms).
 constexpr int kRegGroups = 4;
-constexpr int32_t kRegClusters = kRegGroups * kWave * 4;
+static_assert(kRegGroups * kWave * 4 == kRegClusters, "register groups cover kRegClusters");
 
 __device__ inline void walk_dense_reg(const float4* __restrict__ S, int32_t kr4, float v,
                                       float4 (&acc)[kRegGroups], int lane) {

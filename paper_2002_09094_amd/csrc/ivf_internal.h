@@ -13,6 +13,9 @@ namespace ivf {
 constexpr int kWave = 64;
 constexpr int kLdsBytes = 160 * 1024;      // LDS per CU (and per workgroup) on gfx950
 constexpr int kMaxWaves = 16;
+// FP32 cluster ranges of at most this many clusters take the register walk
+// (each lane holds 16 of the range's scores in registers).
+constexpr int32_t kRegClusters = 1024;
 
 // Launch plan of the assignment walk (chosen by make_plan).
 struct Plan {

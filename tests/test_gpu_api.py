@@ -149,11 +149,10 @@ def test_batch_multi_iteration_calls_and_tuning_report():
     tuning = b.tuning
     assert len(tuning) == 5 and all(ms > 0 for (_, _, ms) in tuning)
     assert b.plan["kr_max"] == min(tuning, key=lambda t: t[2])[0]
-    # then the dense-slab threshold on that shape, the default first
+    # then the dense-slab threshold on that shape
     thetas = b.threshold_tuning
-    assert [round(t, 6) for (t, _) in thetas] == [0.35, 0.5, 0.65]
+    assert [round(t, 6) for (t, _) in thetas] == [0.35, 0.45, 0.5, 0.65]
     assert all(ms > 0 for (_, ms) in thetas)
-    assert thetas[0][1] == min(ms for (_, _, ms) in tuning)
     for i, (x, _, _, _, seeds) in enumerate(inst):
         ref = list(oracle.chain(x, seeds, 6))
         assert np.array_equal(ba[i].cpu().numpy(), ref[-1].assign.assign)

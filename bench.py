@@ -978,6 +978,8 @@ def run_single(args):
         "assign_ms": 1e3 * assign_s / len(per),
         "walk_ms": 1e3 * walk_avg_s,
         "update_ms": sum(p[1]["update_ms"] for p in per) / len(per),
+        "walk_ms_per_step": [p[0]["walk_ms"] for p in per],
+        "update_ms_per_step": [p[1]["update_ms"] for p in per],
         "certified_fraction": sum(p[0]["certified"] for p in per) / (len(per) * x.n),
         "rescored_per_iter": sum(p[0]["rescored"] for p in per) / len(per),
         "max_rel_err_rescored": max(p[0]["max_rel_err_rescored"] for p in per),

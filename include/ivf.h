@@ -88,7 +88,10 @@ typedef struct {
     int32_t certify;        /* 1: certify every argmax, re-score uncertified objects in
                                FP64 (assignments equal the FP64 reference); 0: take the
                                FP32 argmax as is (for timing studies only) */
-    int32_t cluster_range;  /* clusters per LDS score tile; 0: planner's choice */
+    int32_t cluster_range;  /* clusters per range (one score tile per wave: FP32 values in
+                               ranges of at most 1,024 clusters keep it in registers, other
+                               ranges in LDS); 0: planner's choice (1,024 for FP32 values,
+                               1,280 for 16-bit ones) */
     int32_t waves_per_wg;   /* waves (each owning one tile) per workgroup; 0: planner */
     int32_t objects_per_item; /* objects per work-queue item; 0: planner */
     int32_t force_rescore;  /* test hook: 1 = treat every object as uncertified */

@@ -1645,18 +1645,26 @@ ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
         g_build_error = msg;
         return st;
     };
+    // a HIP failure while building: the batch is destroyed and the message kept
+#define BUILD_HIP(call)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return bail(bfail(b, e_ == hipErrorOutOfMemory ? IVF_ERR_OOM : IVF_ERR_HIP,  \
+                              std::string(#call) + ": " + hipGetErrorString(e_)));       \
+    } while (0)
     b->opt = o;
     // graph capture needs a stream of its own (never the null stream)
     if (o.stream) {
         b->stream = reinterpret_cast<hipStream_t>(o.stream);
     } else {
-        BHIP(b, hipStreamCreate(&b->stream));
+        BUILD_HIP(hipStreamCreate(&b->stream));
         b->own_stream = true;
     }
     b->opt.stream = b->stream;
     int dev = 0;
-    BHIP(b, hipGetDevice(&dev));
-    BHIP(b, hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    BUILD_HIP(hipGetDevice(&dev));
+    BUILD_HIP(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev));
     {
         std::vector<int32_t> order(count);
         for (int32_t i = 0; i < count; ++i) order[i] = i;
@@ -1673,17 +1681,17 @@ ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
         }
     }
     for (int l = 0; l < ivf_batch::kLanes; ++l) {
-        BHIP(b, hipStreamCreate(&b->lane[l]));   // default priority
-        BHIP(b, hipEventCreateWithFlags(&b->join_ev[l], hipEventDisableTiming));
+        BUILD_HIP(hipStreamCreate(&b->lane[l]));   // default priority
+        BUILD_HIP(hipEventCreateWithFlags(&b->join_ev[l], hipEventDisableTiming));
         b->lane_sc[l] = new (std::nothrow) Scratch();
         if (!b->lane_sc[l]) return bail(bfail(b, IVF_ERR_OOM, "host allocation failed"));
         // a lane's scratch is sized for its largest instance up front
         int64_t maxnnz = 1;
         for (int32_t i = 0; i < count; ++i)
             if (b->lane_of[i] == l) maxnnz = std::max(maxnnz, X[i].nnz);
-        BHIP(b, b->lane_sc[l]->ensure(maxnnz, maxnnz, 1, b->stream));
+        BUILD_HIP(b->lane_sc[l]->ensure(maxnnz, maxnnz, 1, b->stream));
     }
-    BHIP(b, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+    BUILD_HIP(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
     ivf_options oi = b->opt;
     oi.cluster_range = o.cluster_range > 0 ? o.cluster_range : 1280;
     oi.waves_per_wg = 1;
@@ -1704,22 +1712,23 @@ ivf_status ivf_batch_build(int32_t count, const ivf_csr* X, const int32_t* k,
         }
         b->h.push_back(h);
     }
-    BHIP(b, dalloc(&b->d_args, count));
-    BHIP(b, dalloc(&b->d_item_off, count + 1));
-    BHIP(b, dalloc(&b->d_flags, count));
-    BHIP(b, dalloc(&b->d_cnt, count));
+    BUILD_HIP(dalloc(&b->d_args, count));
+    BUILD_HIP(dalloc(&b->d_item_off, count + 1));
+    BUILD_HIP(dalloc(&b->d_flags, count));
+    BUILD_HIP(dalloc(&b->d_cnt, count));
     {
         std::vector<Counters*> cp(count);
         for (int32_t i = 0; i < count; ++i) cp[i] = b->h[i]->cnt;
-        BHIP(b, hipMemcpy(b->d_cnt, cp.data(), sizeof(Counters*) * count, hipMemcpyHostToDevice));
+        BUILD_HIP(hipMemcpy(b->d_cnt, cp.data(), sizeof(Counters*) * count, hipMemcpyHostToDevice));
     }
-    for (auto& e : b->ev) BHIP(b, hipEventCreate(&e));
-    BHIP(b, dalloc(&b->d_stamp, 2));
-    BHIP(b, dalloc(&b->d_work, 1));
-    BHIP(b, hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev));
+    for (auto& e : b->ev) BUILD_HIP(hipEventCreate(&e));
+    BUILD_HIP(dalloc(&b->d_stamp, 2));
+    BUILD_HIP(dalloc(&b->d_work, 1));
+    BUILD_HIP(hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev));
     if (b->clock_khz <= 0) return bail(bfail(b, IVF_ERR_HIP, "no device wall clock rate"));
     ivf_status st = batch_plan(b, oi.cluster_range, o.waves_per_wg > 0 ? o.waves_per_wg : 8);
     if (st != IVF_OK) return bail(st);
+#undef BUILD_HIP
     *out = b;
     return IVF_OK;
 }

@@ -247,6 +247,21 @@ def test_cert_bound_holds_below_the_normal_range(vt, fused):
     assert relative_alone_fails > 0
 
 
+def test_batch_build_failure_keeps_its_message():
+    """A HIP failure while a batch is built (here: no GPU, so the first HIP
+    call fails) returns IVF_ERR_HIP, no batch, and a message naming the call."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("needs a machine without a usable GPU")
+    lib = _lib.get()
+    b = ctypes.c_void_p()
+    xs = (_lib.ivf_csr * 1)(_lib.ivf_csr(10, 5, 20, 1, 1, 1))
+    ks = (ctypes.c_int32 * 1)(3)
+    assert lib.ivf_batch_build(1, xs, ks, None, ctypes.byref(b)) == -7
+    assert b.value is None
+    assert lib.ivf_batch_last_error(None).startswith(b"hip")
+
+
 def test_batch_build_rejects_bad_arguments_before_any_launch():
     lib = _lib.get()
     b = ctypes.c_void_p()

@@ -98,6 +98,14 @@ SIGNATURES = {
 
 
 def load(path: str = LIB_PATH):
+    # PyTorch supplies the device memory and streams the library works on, and
+    # its HIP runtime must be the process's only one: loaded first, it also
+    # serves the library; loading the library first would start the system's
+    # runtime beside it, whose calls then find no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError("libivf.so is not built (run __graft_entry__.build() or "
                           "python -m paper_2002_09094_amd.build): " + path)

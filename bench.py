@@ -53,7 +53,7 @@ def iteration_bytes(m, nnz, n, ranges, nnz_means, valtype):
             + nnz_means * (12 + 12 + ENTRY_BYTES[valtype]))
 
 
-def kernel_hash(sources=("assign.hip", "invfile.hip", "api.hip")):
+def kernel_hash(sources=("assign.hip", "invfile.hip", "plan.hip")):
     """Hash of a kernel's sources and the shared headers: by default the
     walk's kernels, the inverted-file layout they read (slabs, postings) and
     the planner that picks their plan."""
@@ -381,9 +381,9 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
 
 
 # the walk's counters also depend on the plan (range width, slab threshold),
-# which the planner in api.hip chooses
-KERNEL_SOURCE = {"k_walk": ("assign.hip", "invfile.hip", "api.hip"),
-                 "k_walk_batch": ("assign.hip", "invfile.hip", "api.hip"),
+# which the planner in plan.hip chooses
+KERNEL_SOURCE = {"k_walk": ("assign.hip", "invfile.hip", "plan.hip"),
+                 "k_walk_batch": ("assign.hip", "invfile.hip", "plan.hip"),
                  "k_ivfd_walk": ("ivfd.hip",)}
 
 

@@ -177,5 +177,8 @@ hipError_t radix_sort_pairs_u64(uint32_t* keys, uint2* vals, uint32_t* keys_alt,
 
 // Plan of the walk for k clusters.
 ivf_status make_plan(int32_t k, const ivf_options* o, Plan* p, std::string* err);
+// Default dense-slab threshold of a plan (a slice holding at least this share
+// of its range's clusters is stored as a dense slab).
+float dense_default(int32_t valtype, int32_t k_r);
 
 }  // namespace ivf

@@ -380,6 +380,54 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
         f.write("\n".join(lines) + "\n")
 
 
+def summarize_update_trace(trace_csv, out_txt, command, top=12):
+    """Per-iteration kernel times of the update from a rocprofv3 kernel trace
+    (columns Kernel_Name, Start_Timestamp, End_Timestamp): the launches
+    between one walk launch and the next are that iteration's merge, update
+    and rebuild; the merge of the ranges and the objective belong to the
+    assignment step and are left out of the update's busy time."""
+    import re
+    rows = _csv_rows(trace_csv)
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    assign_side = ("k_merge", "k_rescore", "k_objective", "k_sum_final")
+    iters, cur = [], None
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "copyBuffer" in name or "k_read" in name:
+            continue
+        if re.search(r"::k_walk", name):
+            if cur is not None:
+                iters.append(cur)
+            cur = []
+            continue
+        if cur is not None:
+            cur.append(r)
+    if cur:
+        iters.append(cur)
+    lines = ["# rocprofv3 kernel trace: update kernels per Lloyd iteration",
+             "# command: " + command,
+             "# iteration i: the launches after walk launch i (the first walk starts from "
+             "the seed means); busy = summed kernel time of the update and rebuild", ""]
+    for i, it in enumerate(iters):
+        agg = {}
+        for r in it:
+            m = re.search(r"(k_[a-z0-9_]+)", r["Kernel_Name"])
+            key = m.group(1) if m else r["Kernel_Name"][:30]
+            a = agg.setdefault(key, [0, 0.0])
+            a[0] += 1
+            a[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        busy = sum(v[1] for k, v in agg.items() if k not in assign_side)
+        if busy == 0.0:
+            continue
+        lines.append("iteration %d: update busy %.2f ms" % (i + 1, busy))
+        for k, v in sorted(agg.items(), key=lambda x: -x[1][1])[:int(top)]:
+            if k in assign_side:
+                continue
+            lines.append("    %-24s x%-3d %8.3f ms" % (k, v[0], v[1]))
+    with open(out_txt, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 # the walk's counters also depend on the plan (range width, slab threshold),
 # which the planner in plan.hip chooses
 KERNEL_SOURCE = {"k_walk": ("assign.hip", "invfile.hip", "plan.hip"),
@@ -834,6 +882,9 @@ def batched_cpu_baseline(inst, data, before, after, target_s):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-trace":
         summarize_trace(*sys.argv[2:6])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "summarize-update-trace":
+        summarize_update_trace(*sys.argv[2:5])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "summarize-pmc":
         summarize_pmc(*sys.argv[2:])

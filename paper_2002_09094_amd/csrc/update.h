@@ -108,7 +108,7 @@ struct DeltaArgs {
     const int64_t* off;          // [n + 1]
     int64_t entries;
     const int16_t* shift;
-    int64_t* size;               // [k]
+    int64_t* size;               // [k] in: the sizes of old_assign; out: those of assign
     int64_t* scal;
     // work buffers of >= entries elements
     uint32_t* keys;

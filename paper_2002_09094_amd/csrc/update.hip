@@ -370,10 +370,47 @@ __global__ void k_norm_items(const int64_t* __restrict__ size, const int64_t* __
     items[j] = size[j] > 0 ? (len + kNormChunk - 1) / kNormChunk : 0;
 }
 
+// First place p in [lo, hi) with a[p] >= x (hi when there is none), a sorted
+// a, searched from the guess g: steps of doubling length away from g bracket
+// the place, which bisection then finds.  A guess off by m costs about
+// 2 log2(m) reads, one when it is right.
+__device__ inline int64_t seek_i32(const int32_t* a, int64_t lo, int64_t hi, int64_t g,
+                                   int32_t x) {
+    g = g < lo ? lo : (g > hi ? hi : g);
+    int64_t l, r;   // the place lies in [l, r]
+    if (g < hi) {
+        const int32_t v = a[g];
+        if (v == x) return g;
+        if (v < x) {   // above g
+            l = g + 1;
+            r = hi;
+            for (int64_t step = 1;; step <<= 1) {
+                const int64_t q = g + step;
+                if (q >= hi) break;
+                if (a[q] >= x) { r = q; break; }
+                l = q + 1;
+            }
+            return lower_bound_i32(a, l, r, x);
+        }
+    }
+    // a[g] > x, or g == hi: at or below g
+    l = lo;
+    r = g;
+    for (int64_t step = 1;; step <<= 1) {
+        const int64_t q = g - step;
+        if (q < lo) break;
+        if (a[q] < x) { l = q + 1; break; }
+        r = q;
+    }
+    return lower_bound_i32(a, l, r, x);
+}
+
 // One wave per work item (the scanned item offsets locate its cluster):
 // partial FP64 sums over one chunk of the cluster's segments of w^2, with
 // w = s / |C_j|, and of mu_j(old) . s (the exact objective's share).
-// Lane-strided partials and a fixed butterfly: deterministic.
+// Lane-strided partials and a fixed butterfly: deterministic.  The old row
+// differs little from the new one, so each term is sought from the place the
+// previous step's last term had, moved by the distance between the two.
 __global__ __launch_bounds__(kThreads) void k_norm_parts(UpdateArgs a) {
     const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int lane = lane_id();
@@ -390,19 +427,22 @@ __global__ __launch_bounds__(kThreads) void k_norm_parts(UpdateArgs a) {
     const int64_t ob = a.old_ptr[j], oe = a.old_ptr[j + 1];
     const double dn = (double)a.size[j];
     double ss = 0.0, op = 0.0;
-    int64_t from = ob;   // a lane's terms ascend, so its old-row cursor only moves on
-    const int64_t row0 = a.cstart[j];
-    for (int64_t s = s0 + lane; s < s1; s += kWave) {
-        const double sv = seg_value(a.seg_acc, a.seg_t, a.shift, s);
-        const double w = sv / dn;
-        ss += w * w;
-        const int32_t t = a.seg_t[s];
-        // the old row's support differs little from the new one's: term t is
-        // usually at the same rank there; else search what is left of the row
-        int64_t p = ob + (s - row0);
-        if (!(p >= from && p < oe && a.old_idx[p] == t)) p = lower_bound_i32(a.old_idx, from, oe, t);
-        from = p;
-        if (p < oe && a.old_idx[p] == t) op += a.old_val[p] * sv;
+    int64_t from = ob;                 // wave-uniform: no term of this step lies before it
+    int64_t off = ob - a.cstart[j];    // wave-uniform: old place minus new place, guessed
+    for (int64_t base = s0; base < s1; base += kWave) {   // wave-uniform trip count
+        const int64_t s = base + lane;
+        int64_t p = from;
+        if (s < s1) {
+            const double sv = seg_value(a.seg_acc, a.seg_t, a.shift, s);
+            const double w = sv / dn;
+            ss += w * w;
+            const int32_t t = a.seg_t[s];
+            p = seek_i32(a.old_idx, from, oe, s + off, t);
+            if (p < oe && a.old_idx[p] == t) op += a.old_val[p] * sv;
+        }
+        const int last = s1 - 1 - base < kWave - 1 ? (int)(s1 - 1 - base) : kWave - 1;
+        from = readlane_i64(p, last);
+        off = from - (base + last);
     }
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) {
@@ -438,17 +478,21 @@ __global__ void k_norm_final(UpdateArgs a) {
     a.newcnt[j] = a.cstart[j + 1] - a.cstart[j];
 }
 
-__global__ __launch_bounds__(kThreads) void k_fill(UpdateArgs a) {
-    const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+// The new rows.  Waves below norm_items[k] take one work item each (a chunk
+// of kNormChunk segments of a cluster with members, as in the norm pass, so
+// one huge cluster does not hold up the launch); wave item_cap + j copies the
+// old row of cluster j when it has no members.
+__global__ __launch_bounds__(kThreads) void k_fill(UpdateArgs a, int64_t item_cap) {
+    const int64_t it = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int lane = lane_id();
-    if (j >= a.k) return;
-    const int64_t nj = a.size[j];
-    const int64_t p0 = a.new_ptr[j];
     if (a.new_ptr[a.k] > a.new_cap) {   // the new means do not fit: flag, write nothing
-        if (j == 0 && lane == 0) atomicOr(&a.cnt->error_flags, (unsigned long long)kOverflow);
+        if (it == 0 && lane == 0) atomicOr(&a.cnt->error_flags, (unsigned long long)kOverflow);
         return;
     }
-    if (nj == 0) {
+    if (it >= item_cap) {
+        const int64_t j = it - item_cap;
+        if (j >= a.k || a.size[j] != 0) return;
+        const int64_t p0 = a.new_ptr[j];
         const int64_t ob = a.old_ptr[j], oe = a.old_ptr[j + 1];
         for (int64_t e = ob + lane; e < oe; e += kWave) {
             a.new_idx[p0 + (e - ob)] = a.old_idx[e];
@@ -457,13 +501,23 @@ __global__ __launch_bounds__(kThreads) void k_fill(UpdateArgs a) {
         }
         return;
     }
-    const int64_t s0 = a.cstart[j], s1 = a.cstart[j + 1];
-    const double dn = (double)nj, nr = a.nrm[j];
+    if (it >= a.norm_items[a.k]) return;
+    int64_t lo = 0, hi = a.k;   // last cluster j with norm_items[j] <= it
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.norm_items[mid] <= it) lo = mid; else hi = mid;
+    }
+    const int64_t j = lo;
+    const int64_t row0 = a.cstart[j];
+    const int64_t s0 = row0 + (it - a.norm_items[j]) * kNormChunk;
+    const int64_t s1 = min(a.cstart[j + 1], s0 + kNormChunk);
+    const int64_t p0 = a.new_ptr[j];
+    const double dn = (double)a.size[j], nr = a.nrm[j];
     for (int64_t s = s0 + lane; s < s1; s += kWave) {
         const double w = seg_value(a.seg_acc, a.seg_t, a.shift, s) / dn;
-        a.new_idx[p0 + (s - s0)] = a.seg_t[s];
-        a.new_val[p0 + (s - s0)] = w / nr;
-        a.new_row[p0 + (s - s0)] = (int32_t)j;
+        a.new_idx[p0 + (s - row0)] = a.seg_t[s];
+        a.new_val[p0 + (s - row0)] = w / nr;
+        a.new_row[p0 + (s - row0)] = (int32_t)j;
     }
 }
 
@@ -513,30 +567,56 @@ __global__ void k_delta_count(const int64_t* __restrict__ x_ptr, int64_t n,
     }
 }
 
+// Cluster sizes of `assign` from those of `old_assign`: each changed object
+// leaves its old cluster and joins its new one.
+__global__ void k_delta_sizes(const int32_t* __restrict__ assign,
+                              const int32_t* __restrict__ old_assign, int64_t n, int32_t k,
+                              int64_t* __restrict__ size) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = valid_cluster(assign[i], k), o = valid_cluster(old_assign[i], k);
+        if (a == o) continue;
+        if (o >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(&size[o]), ~0ull);   // -1
+        if (a >= 0) atomicAdd(reinterpret_cast<unsigned long long*>(&size[a]), 1ull);
+    }
+}
+
 // The delta entries of the changed objects at their scanned offsets, keyed by
-// term: payload (cluster | 2^31 if the entry subtracts, FP32 value bits).
+// term: payload (cluster | 2^31 if the entry subtracts, FP32 value bits).  A
+// wave takes 64 consecutive objects and copies the rows of the changed ones
+// one after the other, its lanes reading and writing consecutive entries.
 __global__ void k_delta_emit(const int64_t* __restrict__ x_ptr, const int32_t* __restrict__ x_idx,
                              const float* __restrict__ x_val, int64_t n,
                              const int32_t* __restrict__ assign,
                              const int32_t* __restrict__ old_assign, int32_t k,
                              const int64_t* __restrict__ off, uint32_t* __restrict__ keys,
                              uint2* __restrict__ pay) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (off[i + 1] == off[i]) continue;
-        const int32_t a = valid_cluster(assign[i], k), o = valid_cluster(old_assign[i], k);
-        const int64_t hb = x_ptr[i], he = x_ptr[i + 1];
-        int64_t q = off[i];
-        if (o >= 0)
-            for (int64_t e = hb; e < he; ++e, ++q) {
-                keys[q] = (uint32_t)x_idx[e];
-                pay[q] = make_uint2((uint32_t)o | 0x80000000u, __float_as_uint(x_val[e]));
+    const int lane = lane_id();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;   // objects per sweep of the grid
+    for (int64_t g0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) - lane; g0 < n;
+         g0 += stride) {   // wave-uniform
+        const int64_t i = g0 + lane;
+        uint64_t changed = __ballot(i < n && off[i + 1] != off[i]);
+        while (changed) {
+            const int64_t obj = g0 + (__ffsll((unsigned long long)changed) - 1);
+            changed &= changed - 1;
+            const int32_t a = valid_cluster(assign[obj], k), o = valid_cluster(old_assign[obj], k);
+            const int64_t hb = x_ptr[obj], len = x_ptr[obj + 1] - hb;
+            const int64_t q = off[obj];
+            const int64_t qa = q + (o >= 0 ? len : 0);   // the added copy follows the subtracted one
+            for (int64_t e = lane; e < len; e += kWave) {
+                const uint32_t t = (uint32_t)x_idx[hb + e];
+                const uint32_t v = __float_as_uint(x_val[hb + e]);
+                if (o >= 0) {
+                    keys[q + e] = t;
+                    pay[q + e] = make_uint2((uint32_t)o | 0x80000000u, v);
+                }
+                if (a >= 0) {
+                    keys[qa + e] = t;
+                    pay[qa + e] = make_uint2((uint32_t)a, v);
+                }
             }
-        if (a >= 0)
-            for (int64_t e = hb; e < he; ++e, ++q) {
-                keys[q] = (uint32_t)x_idx[e];
-                pay[q] = make_uint2((uint32_t)a, __float_as_uint(x_val[e]));
-            }
+        }
     }
 }
 
@@ -797,7 +877,10 @@ hipError_t launch_delta_count(const int64_t* x_ptr, int64_t n, const int32_t* as
 }
 
 hipError_t launch_delta_update(DeltaArgs& a, hipStream_t s) {
-    HIP_RET(launch_sizes(a.assign, a.n, a.k, a.size, a.scal, s));
+    // a.size holds the sizes of a.old_assign (the last update's assignment)
+    k_zero_i64<<<1, kThreads, 0, s>>>(a.scal, 4);
+    k_delta_sizes<<<capped(a.n), kThreads, 0, s>>>(a.assign, a.old_assign, a.n, a.k, a.size);
+    HIP_RET(hipGetLastError());
     const int64_t m = a.entries;
     if (m > 0) {
         k_delta_emit<<<capped(a.n), kThreads, 0, s>>>(a.x_ptr, a.x_idx, a.x_val, a.n, a.assign,
@@ -848,7 +931,8 @@ hipError_t launch_copy_table(const int32_t* sj, const int32_t* st, const unsigne
 }
 
 hipError_t launch_update_fill(UpdateArgs& a, hipStream_t s) {
-    k_fill<<<grid_for((int64_t)a.k * kWave), kThreads, 0, s>>>(a);
+    const int64_t items = norm_item_bound(a.k, a.nnz);
+    k_fill<<<grid_for((items + a.k) * kWave), kThreads, 0, s>>>(a, items);
     return hipGetLastError();
 }
 

@@ -145,3 +145,25 @@ def test_level_summary_scales_requests_by_the_probes(tmp_path, monkeypatch):
                                                              "hbm": 1e-4}, 1.0, 1.0)
     assert r["bound"] == "l2" and r["frac"] == pytest.approx(1000.0 * 128 / 2.0 / 1e9 / 1e-4)
     assert r["effective_gbps_algorithmic"] == pytest.approx(1e6 / 2.0 / 1e9)
+
+
+def test_update_trace_summary_splits_iterations_at_the_walk(tmp_path):
+    """Kernels after walk launch i are iteration i's; the assignment side's
+    merge is listed apart from the update's busy time."""
+    merge = "ivf::(anonymous namespace)::k_merge(ivf::MergeArgs)"
+    keys = "ivf::(anonymous namespace)::k_keys(int const*, int const*, long, int, unsigned int*)"
+    fill = "ivf::(anonymous namespace)::k_fill(ivf::UpdateArgs, long)"
+    seq = [("gen", 0, 5), (WALK, 10, 100), (merge, 100, 103), (keys, 103, 107), (fill, 107, 108),
+           (COPY, 108, 200), (WALK, 200, 300), (merge, 300, 303), (fill, 303, 305)]
+    ns = 1_000_000
+    _write(tmp_path / "t.csv", ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           [{"Kernel_Name": n, "Start_Timestamp": a * ns, "End_Timestamp": b * ns}
+            for n, a, b in reversed(seq)])   # any order: sorted by start
+    bench.summarize_update_trace(str(tmp_path / "t.csv"), str(tmp_path / "u.txt"), "cmd")
+    text = (tmp_path / "u.txt").read_text()
+    assert "# command: cmd" in text
+    assert "iteration 1: update busy 5.00 ms" in text
+    assert "iteration 2: update busy 2.00 ms" in text
+    assert "k_merge" not in text and "copyBuffer" not in text and "gen" not in text
+    first = text[text.index("iteration 1"):text.index("iteration 2")]
+    assert first.index("k_keys") < first.index("k_fill")

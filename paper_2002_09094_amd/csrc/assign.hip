@@ -16,6 +16,8 @@
 //              reference does (ascending terms, a separate multiply and add)
 //              and apply the argmax rule.
 //   k_objective / k_sum_final  deterministic FP64 objective and change count.
+#include <algorithm>
+
 #include "ivf_internal.h"
 #include "kernels.h"
 
@@ -604,17 +606,24 @@ __attribute__((amdgpu_waves_per_eu(VT == IVF_VAL_F32 ? 6 : 7, 8))) void k_walk_b
     }
 }
 
-__global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t m = 0;
-    bool zero = false, cert = false;
-    double rel = 0.0;   // the certified winner's relative bound (>= 0)
-    if (i < a.n) {
+constexpr int kMergeBlock = 256;
+
+// Objects in a grid-stride loop; the counters reduced per thread, per wave and
+// per block, then added with one atomic per block and counter.  One atomic
+// per wave on the same four addresses (125,000 waves at 8M objects) queued
+// for 3 ms on one L2 channel.
+__global__ __launch_bounds__(kMergeBlock) void k_merge(MergeArgs a) {
+    int64_t m = 0;                          // entries walked (M)
+    uint32_t n_cert = 0, n_zero = 0;        // certified and zero-overlap objects
+    double rel = 0.0;                       // largest relative bound of a kept FP32 winner
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
         float b = 0.f, s2 = 0.f;
         int32_t id = -1;
+        int64_t mi = 0;
         for (int r = 0; r < a.R; ++r) {
             const RangeRec rec = a.rec[(int64_t)r * a.n + i];
-            m += rec.m;
+            mi += rec.m;
             // ranges arrive in ascending cluster order: an equal best keeps the earlier
             if (rec.best > b) {
                 s2 = fmaxf(fmaxf(s2, b), rec.second);
@@ -624,16 +633,17 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
                 s2 = fmaxf(s2, rec.best);
             }
         }
+        m += mi;
         const int32_t prev = a.prev[i];
         a.best[i] = b;
         a.best_id[i] = id;
         a.second[i] = s2;
         uint8_t flag;
-        if (m == 0) {                      // no term shared with any mean
+        if (mi == 0) {                     // no term shared with any mean
             a.assign[i] = prev;
             a.rho[i] = 0.0;
             flag = 4;
-            zero = true;
+            ++n_zero;
         } else {
             double c, ab, g;
             if (a.fixed_scale > 0.0)
@@ -649,8 +659,8 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
                 a.assign[i] = id >= 0 ? id : prev;
                 a.rho[i] = (double)b;
                 flag = ok ? 1 : 0;
-                cert = ok;
-                rel = c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0);
+                n_cert += ok ? 1u : 0u;
+                rel = fmax(rel, c + (ab > 0.0 && b > 0.f ? ab / (double)b : 0.0));
             } else {
                 const unsigned long long slot = atomicAdd(&a.cnt->n_rescore, 1ull);
                 a.rescore_list[slot] = (int32_t)i;
@@ -659,21 +669,37 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
         }
         a.flags[i] = flag;
     }
-    // the entries walked (M), the certified and zero-overlap counts and the
-    // largest bound, reduced per wave: one atomic per wave and counter rather
-    // than one per object on a single address (non-negative doubles order
-    // like their bit patterns)
+    // integer sums and a maximum: the same in any order (non-negative
+    // doubles order like their bit patterns)
 #pragma unroll
     for (int o = kWave / 2; o >= 1; o >>= 1) {
         m += __shfl_xor(m, o, kWave);
+        n_cert += __shfl_xor(n_cert, o, kWave);
+        n_zero += __shfl_xor(n_zero, o, kWave);
         rel = fmax(rel, __shfl_xor(rel, o, kWave));
     }
-    const unsigned long long n_cert = __popcll(__ballot(cert));
-    const unsigned long long n_zero = __popcll(__ballot(zero));
+    constexpr int W = kMergeBlock / kWave;
+    __shared__ int64_t s_m[W];
+    __shared__ uint32_t s_cert[W], s_zero[W];
+    __shared__ double s_rel[W];
+    const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
+        s_m[w] = m;
+        s_cert[w] = n_cert;
+        s_zero[w] = n_zero;
+        s_rel[w] = rel;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < W; ++q) {
+            m += s_m[q];
+            n_cert += s_cert[q];
+            n_zero += s_zero[q];
+            rel = fmax(rel, s_rel[q]);
+        }
         if (m) atomicAdd(&a.cnt->mult, (unsigned long long)m);
-        if (n_cert) atomicAdd(&a.cnt->certified, n_cert);
-        if (n_zero) atomicAdd(&a.cnt->zero_overlap, n_zero);
+        if (n_cert) atomicAdd(&a.cnt->certified, (unsigned long long)n_cert);
+        if (n_zero) atomicAdd(&a.cnt->zero_overlap, (unsigned long long)n_zero);
         if (rel > 0.0)
             atomicMax(&a.cnt->max_bound_bits, (unsigned long long)__double_as_longlong(rel));
     }
@@ -951,8 +977,9 @@ const void* rescore_kernel_ptr(int valtype) {
 }
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
-    const int64_t blocks = (a.n + 255) / 256;
-    if (blocks > 0) k_merge<<<(unsigned)blocks, 256, 0, s>>>(a);
+    // eight blocks per CU at most; every object is one thread's in the loop
+    const int64_t blocks = std::min<int64_t>((a.n + kMergeBlock - 1) / kMergeBlock, 2048);
+    if (blocks > 0) k_merge<<<(unsigned)blocks, kMergeBlock, 0, s>>>(a);
     return hipGetLastError();
 }
 

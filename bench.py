@@ -364,6 +364,8 @@ def summarize_trace(stats_csv, out_txt, command, note=""):
     if os.path.exists(trace_csv):
         top = rows[0]["Name"]
         launches = [r for r in _csv_rows(trace_csv) if r["Kernel_Name"] == top]
+        if not launches:   # a trace of another run
+            raise ValueError("%s holds no launch of %s" % (trace_csv, top))
         ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in launches]
         short = top.replace("ivf::(anonymous namespace)::", "").split("(")[0]
         lines += ["", "%s launches in order (ms): %s" % (short, ", ".join("%.3f" % v for v in ms))]

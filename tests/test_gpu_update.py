@@ -73,6 +73,12 @@ def _lockstep(x, k, iters, opts, seeds=None, means=None):
     (20000, 10000, 50.0, 5, 200, 1.1, 100, 11, {}),
     (9000, 3000, 25.0, 0, 120, 1.05, 700, 12, {"cluster_range": 64}),
     (6000, 4000, 60.0, 10, 400, 1.2, 37, 13, {"objects_per_item": 3, "waves_per_wg": 5}),
+    # wide vocabularies: term keys of 17 and 18 bits sort in two 9-bit
+    # passes (the inverted file and the incremental update's term order),
+    # 19 bits in three 8-bit passes and a copy back
+    (15000, 120000, 40.0, 5, 200, 1.1, 80, 14, {}),
+    (12000, 262144, 40.0, 5, 200, 1.1, 60, 15, {}),
+    (12000, 300000, 40.0, 5, 200, 1.1, 60, 16, {}),
 ])
 def test_incremental_update_equals_the_full_reduction(shape):
     n, d, lam, lo, hi, s, k, seed, opts = shape

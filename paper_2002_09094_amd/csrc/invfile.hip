@@ -123,21 +123,26 @@ __global__ void k_desc(const int64_t* ptr, const int32_t* cid, int64_t d, int32_
         ds.count = (int32_t)cnt;
         desc[t * R + r] = ds;
         // a dense slab's size is rounded up to whole 128-byte lines, so every
-        // slab starts on a line (0.5-0.8 % faster walks at 8M documents)
-        dsz[t * R + r] = (cnt > 0 && (float)cnt >= theta * (float)kr)
+        // slab starts on a line (0.5-0.8 % faster walks at 8M documents); the
+        // sizes are laid out range-major, so a range's slabs are contiguous
+        dsz[(int64_t)r * d + t] = (cnt > 0 && (float)cnt >= theta * (float)kr)
                              ? (int64_t)((kr + align - 1) / align * align)
                              : 0;
         lo = hi;
     }
 }
 
-__global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, int64_t nslices,
+__global__ void k_desc_dense(SliceDesc* desc, const int64_t* doff, int64_t d, int32_t R,
                              int64_t cap) {
-    // a slice is dense iff its scanned offset grows: doff[s + 1] > doff[s];
-    // one that would not fit the slab capacity stays sparse (same scores)
+    // slice (t, r) is desc[t * R + r], its scanned slab offset doff[r * d + t];
+    // a slice is dense iff that offset grows to the next entry; one that would
+    // not fit the slab capacity stays sparse (same scores)
+    const int64_t nslices = d * R;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslices;
-         s += (int64_t)gridDim.x * blockDim.x)
-        if (doff[s + 1] > doff[s] && doff[s + 1] <= cap) desc[s].pos = (int32_t)(-(doff[s] + 1));
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t o = (s % R) * d + s / R;
+        if (doff[o + 1] > doff[o] && doff[o + 1] <= cap) desc[s].pos = (int32_t)(-(doff[o] + 1));
+    }
 }
 
 template <typename T>
@@ -201,7 +206,7 @@ hipError_t launch_build_slabs(IvfArgs& a, int64_t slab_cap, hipStream_t s) {
     // slab_cap: elements the slab array holds; the needed total is at dsz[d * R]
     const int64_t ns = a.d * a.R;
     if (slab_cap <= 0) return hipSuccess;
-    k_desc_dense<<<capped(ns), kThreads, 0, s>>>(a.desc, a.dsz, ns, slab_cap);
+    k_desc_dense<<<capped(ns), kThreads, 0, s>>>(a.desc, a.dsz, a.d, a.R, slab_cap);
     const int64_t* total = a.dsz + ns;
     if (a.valtype == IVF_VAL_F32)
         k_zero_t<float><<<capped(slab_cap), kThreads, 0, s>>>(reinterpret_cast<float*>(a.slab),

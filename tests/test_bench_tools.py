@@ -167,3 +167,13 @@ def test_update_trace_summary_splits_iterations_at_the_walk(tmp_path):
     assert "k_merge" not in text and "copyBuffer" not in text and "gen" not in text
     first = text[text.index("iteration 1"):text.index("iteration 2")]
     assert first.index("k_keys") < first.index("k_fill")
+
+
+def test_trace_summary_refuses_a_trace_of_another_run(tmp_path):
+    stats = tmp_path / "x_kernel_stats.csv"
+    _write(stats, ["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage"],
+           [{"Name": WALK, "Calls": 1, "TotalDurationNs": 1e9, "AverageNs": 1e9, "Percentage": 100}])
+    _write(tmp_path / "x_kernel_trace.csv", ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+           [{"Kernel_Name": IVFD, "Start_Timestamp": 0, "End_Timestamp": 5}])
+    with pytest.raises(ValueError, match="no launch"):
+        bench.summarize_trace(str(stats), str(tmp_path / "s.txt"), "cmd")
